@@ -1,0 +1,148 @@
+/*
+ * pn.h -- C interface of the MI355X (gfx950) batched post-Newtonian
+ * inspiral integrator.
+ *
+ * The library integrates many independent binary-black-hole inspirals, each
+ * the ODE system of the paper (Herrmann et al., arXiv:0908.3889, Sec. II):
+ *   state  y = (omega, S1[3], S2[3], L_hat[3])
+ *   Eq. (1) d omega/dt (to 3.5PN, with 1.5PN spin-orbit and 2PN spin-spin),
+ *   Eq. (2) dS_i/dt = Omega_i x S_i,  Eq. (3) dL_hat/dt,
+ *   Eq. (4) Omega_1 (and Omega_2 by 1 <-> 2),
+ * from omega0 to omega_f with the adaptive Dormand-Prince method at error
+ * tolerance tol and initial step h = 10 (Sec. II).  One GPU lane integrates
+ * one inspiral at a time; a persistent kernel hands new inspirals to lanes
+ * as theirs finish.
+ *
+ * Conventions for every entry point:
+ *  - Arrays are structure-of-arrays of float64 (int32 where stated): component
+ *    c of inspiral i lives at p[c*ld + i], with leading dimension ld >= n.
+ *  - Every array pointer is a DEVICE pointer on the current HIP device,
+ *    allocated and owned by the caller; the library never frees it.  Inputs
+ *    are read only; outputs are written for every i < n.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Calls are
+ *    asynchronous on that stream: they return once the work is enqueued.  The
+ *    library never synchronises the device, prints or aborts.
+ *  - The return value is PN_OK (0) when the work was enqueued, or a negative
+ *    PN_E* code: PN_EINVAL for bad arguments (nothing is launched),
+ *    PN_ENODEV when no usable gfx950 device is current, PN_EHIP when a HIP
+ *    call or launch failed (checked after every launch).  pn_strerror()
+ *    names a code.
+ *  - Outcomes per inspiral go to status[i] (PN_ST_*), never to the return code.
+ *  - Safe to call from several host threads on different streams.  The
+ *    library keeps a small per-device context (a work counter per call slot
+ *    and the device's compute-unit count), created on first use.
+ */
+#ifndef PN_H
+#define PN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes ---------------------------------------------------- */
+#define PN_OK        0
+#define PN_EINVAL   -1   /* invalid argument */
+#define PN_ENODEV   -2   /* no usable device */
+#define PN_EHIP     -3   /* a HIP runtime call or kernel launch failed */
+#define PN_ENOMEM   -4   /* the library could not allocate its device context */
+
+/* ---- per-inspiral status codes (status[i]) --------------------------- */
+#define PN_ST_OK                    0  /* reached omega_f (or t_end) */
+#define PN_ST_DONE_AT_START         1  /* omega0 >= omega_f: no step, y_final = y0, t = 0 */
+#define PN_ST_MAX_STEPS            -1  /* accepted + rejected steps reached max_steps */
+#define PN_ST_H_UNDERFLOW          -2  /* step size fell below 1e-14 of the independent variable */
+#define PN_ST_NONFINITE            -3  /* NaN error estimate or non-finite candidate state */
+#define PN_ST_BAD_INPUT            -4  /* m_i <= 0, omega0 <= 0 or a non-finite input */
+#define PN_ST_OMEGADOT_NONPOSITIVE -5  /* d omega/dt <= 0 at the start of a step */
+
+/* ---- which terms of Eqs. (1)-(4) are on (bitmask) --------------------- */
+#define PN_TERM_PN       1   /* non-spinning corrections of Eq. (1), (M w)^{2/3} ... (M w)^{7/3} */
+#define PN_TERM_SO_WDOT  2   /* spin-orbit term of Eq. (1) */
+#define PN_TERM_SS_WDOT  4   /* spin-spin term of Eq. (1) */
+#define PN_TERM_RR       8   /* d omega/dt itself; off => omega is constant */
+#define PN_TERM_SO_PREC 16   /* the L_hat part of Eq. (4) */
+#define PN_TERM_SS_PREC 32   /* the S_j - 3 (S_j . L_hat) L_hat part of Eq. (4) */
+#define PN_TERM_ALL     63
+
+/* ---- scheduling -------------------------------------------------------- */
+#define PN_SCHED_PERSISTENT 0  /* resident grid; lanes take new inspirals as theirs finish */
+#define PN_SCHED_STATIC     1  /* one lane per inspiral, no refill */
+
+/* Options.  A zero-initialised struct (or a NULL pointer) gives the paper's
+ * settings: adaptive Dormand-Prince, h0 = 10, all terms, omega_f termination. */
+typedef struct pn_opts {
+    double  h0;            /* initial step in units of M; <= 0 -> 10 (Sec. II) */
+    double  h_fixed;       /* > 0: fixed step h_fixed, no error control */
+    double  t_end;         /* > 0: integrate to t = t_end instead of omega_f */
+    int64_t max_steps;     /* per inspiral, accepted + rejected; <= 0 -> 10,000,000 */
+    int32_t terms;         /* PN_TERM_* mask; <= 0 -> PN_TERM_ALL */
+    int32_t theta_literal; /* 0: theta_hat multiplies eta once in the 3PN term (the
+                              expansion the paper cites); 1: the extra factor eta
+                              exactly as printed in Eq. (1) */
+    int32_t schedule;      /* PN_SCHED_* */
+    int32_t block;         /* threads per block, a multiple of 64 in [64, 1024]; 0 -> 256 */
+    int32_t waves_per_simd;/* persistent grid: waves per SIMD (1..8); 0 -> 2 */
+    int32_t refill_min;    /* persistent: a wave refills once this many of its lanes
+                              are idle (1..64); 0 -> 1 */
+} pn_opts;
+
+/*
+ * pn_integrate -- integrate n inspirals from omega0 to omega_f (Sec. II).
+ *
+ * Inputs (device, float64, SoA with leading dimension ld):
+ *   m      [2][ld]  masses m1, m2 (> 0).  The equations are scale free; the
+ *                   paper fixes M = m1 + m2 = 1 (Sec. II).
+ *   S0     [6][ld]  initial spins S1 (x,y,z), S2 (x,y,z); S_i = chi_i m_i^2 S_hat_i.
+ *   L0     [3][ld]  initial unit orbital angular momentum direction L_hat.
+ *   omega0 [ld]     initial orbital frequency (> 0).
+ *   omega_f         termination frequency (> 0; ignored when opt->t_end > 0).
+ *   tol             error tolerance: absolute and relative tolerance of the
+ *                   root-mean-square error norm over the 10 state components
+ *                   (> 0 unless opt->h_fixed > 0).
+ * Outputs (device):
+ *   y_final [10][ld] final state (omega, S1, S2, L_hat); omega = omega_f exactly
+ *                    on PN_ST_OK.  On a failure status: the last accepted state.
+ *   t_final [ld]     elapsed time t (units of M).
+ *   steps   [3][ld]  int32: accepted steps (time steps + final omega-steps),
+ *                    rejected steps, right-hand-side evaluations.
+ *   status  [ld]     int32 PN_ST_* code.
+ *   dots    [3][ld]  optional (may be NULL): S1_hat.S2_hat, S1_hat.L_hat,
+ *                    S2_hat.L_hat of the final state (0 where a norm is 0),
+ *                    the observables of Sec. V.
+ * n = 0 is valid and launches nothing.
+ */
+int pn_integrate(int64_t n, int64_t ld,
+                 const double* m, const double* S0, const double* L0, const double* omega0,
+                 double omega_f, double tol, const pn_opts* opt,
+                 double* y_final, double* t_final, int32_t* steps, int32_t* status,
+                 double* dots, void* stream);
+
+/*
+ * pn_rhs -- Eqs. (1)-(4) evaluated pointwise, dy/dt at y, for testing the
+ * right-hand side on its own.  m [2][ld], y [10][ld] -> dydt [10][ld].
+ * `terms`/`theta_literal` as in pn_opts (opt may be NULL).
+ */
+int pn_rhs(int64_t n, int64_t ld, const double* m, const double* y, double* dydt,
+           const pn_opts* opt, void* stream);
+
+/*
+ * pn_observables -- unit-vector scalar products of Sec. V:
+ * y [10][ld] -> dots [3][ld] = (S1_hat.S2_hat, S1_hat.L_hat, S2_hat.L_hat),
+ * each 0 where one of the norms is 0.
+ */
+int pn_observables(int64_t n, int64_t ld, const double* y, double* dots, void* stream);
+
+/* Name of a PN_* return code (static string). */
+const char* pn_strerror(int code);
+
+/* Library version string (static). */
+const char* pn_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PN_H */

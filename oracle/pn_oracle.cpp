@@ -390,7 +390,10 @@ Result<T> integrate_one(const T& m1, const T& m2, const T* y0, const Mode& md) {
         for (int s = 1; s < 7; ++s) {
             for (int c = 0; c < 10; ++c) {
                 T acc = T(0.0);
-                for (int j = 0; j < s; ++j) acc = acc + rv(DP_A[s][j]) * k[j][c];
+                for (int j = 0; j < s; ++j) {
+                    if (DP_A[s][j].num == 0) continue;          /* structural zero */
+                    acc = acc + rv(DP_A[s][j]) * k[j][c];
+                }
                 Y[c] = y[c] + htry * acc;
             }
             deriv(m1, m2, Y, k[s], &dtv[s], omega_mode, md);
@@ -404,7 +407,10 @@ Result<T> integrate_one(const T& m1, const T& m2, const T* y0, const Mode& md) {
             T sum = T(0.0);
             for (int c = 0; c < 10; ++c) {
                 T e = T(0.0);
-                for (int j = 0; j < 7; ++j) e = e + (rv(DP_B[j]) - rv(DP_BHAT[j])) * k[j][c];
+                for (int j = 0; j < 7; ++j) {
+                    if (DP_B[j].num == 0 && DP_BHAT[j].num == 0) continue;   /* structural zero */
+                    e = e + (rv(DP_B[j]) - rv(DP_BHAT[j])) * k[j][c];
+                }
                 e = htry * e;
                 const T sc = md.tol + md.tol * tmax(fabs(y[c]), fabs(y5[c]));
                 const T q = e / sc;
@@ -437,7 +443,10 @@ Result<T> integrate_one(const T& m1, const T& m2, const T* y0, const Mode& md) {
             /* accept */
             if (omega_mode) {
                 T dt = T(0.0);
-                for (int j = 0; j < 7; ++j) dt = dt + rv(DP_B[j]) * dtv[j];
+                for (int j = 0; j < 7; ++j) {
+                    if (DP_B[j].num == 0) continue;
+                    dt = dt + rv(DP_B[j]) * dtv[j];
+                }
                 r.t = r.t + htry * dt;
             } else {
                 r.t = r.t + htry;

@@ -1,0 +1,77 @@
+"""ctypes declarations of the C interface in include/pn.h (argument
+marshalling only).  Loading fails loudly when libpn.so has not been built:
+there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpn.so")
+
+# return codes
+PN_OK, PN_EINVAL, PN_ENODEV, PN_EHIP, PN_ENOMEM = 0, -1, -2, -3, -4
+# per-inspiral status
+STATUS = {0: "OK", 1: "DONE_AT_START", -1: "MAX_STEPS", -2: "H_UNDERFLOW", -3: "NONFINITE",
+          -4: "BAD_INPUT", -5: "OMEGADOT_NONPOSITIVE"}
+# term switches
+PN_TERM_PN, PN_TERM_SO_WDOT, PN_TERM_SS_WDOT, PN_TERM_RR = 1, 2, 4, 8
+PN_TERM_SO_PREC, PN_TERM_SS_PREC, PN_TERM_ALL = 16, 32, 63
+# schedules
+PN_SCHED_PERSISTENT, PN_SCHED_STATIC = 0, 1
+
+EXPORTS = ("pn_integrate", "pn_rhs", "pn_observables", "pn_strerror", "pn_version")
+
+
+class PnOpts(C.Structure):
+    _fields_ = [
+        ("h0", C.c_double),
+        ("h_fixed", C.c_double),
+        ("t_end", C.c_double),
+        ("max_steps", C.c_int64),
+        ("terms", C.c_int32),
+        ("theta_literal", C.c_int32),
+        ("schedule", C.c_int32),
+        ("block", C.c_int32),
+        ("waves_per_simd", C.c_int32),
+        ("refill_min", C.c_int32),
+    ]
+
+
+class PnError(RuntimeError):
+    pass
+
+
+_lib = None
+
+
+def load():
+    """The loaded libpn.so (raises if it is missing)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise PnError(f"{LIB_PATH} is not built; run `python -m paper_0908_3889_amd.build` "
+                      "(the GPU path has no fallback)")
+    L = C.CDLL(LIB_PATH)
+    vp, i64, dbl = C.c_void_p, C.c_int64, C.c_double
+    popts = C.POINTER(PnOpts)
+    L.pn_integrate.argtypes = [i64, i64, vp, vp, vp, vp, dbl, dbl, popts, vp, vp, vp, vp, vp, vp]
+    L.pn_integrate.restype = C.c_int
+    L.pn_rhs.argtypes = [i64, i64, vp, vp, vp, popts, vp]
+    L.pn_rhs.restype = C.c_int
+    L.pn_observables.argtypes = [i64, i64, vp, vp, vp]
+    L.pn_observables.restype = C.c_int
+    L.pn_strerror.argtypes = [C.c_int]
+    L.pn_strerror.restype = C.c_char_p
+    L.pn_version.argtypes = []
+    L.pn_version.restype = C.c_char_p
+    _lib = L
+    return L
+
+
+def check(rc: int, what: str) -> None:
+    if rc != PN_OK:
+        msg = load().pn_strerror(rc).decode()
+        raise PnError(f"{what} failed: {msg} ({rc})")

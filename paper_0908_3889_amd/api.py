@@ -1,0 +1,130 @@
+"""Python binding of the gfx950 integrator.
+
+Same names as the C interface (include/pn.h).  Arguments are torch tensors
+on the current HIP device (float64, structure-of-arrays [components, n],
+unit stride along n); the functions only marshal pointers, sizes and the
+current stream into the library.  Every step of the integration runs in the
+library's kernels.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import torch
+
+from . import _lib
+from ._lib import PnOpts, check, load
+
+SCHEDULES = {"persistent": _lib.PN_SCHED_PERSISTENT, "static": _lib.PN_SCHED_STATIC}
+
+
+def _soa(t: torch.Tensor, comps: int, n: int, name: str, dtype=torch.float64) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a torch tensor on the GPU")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}")
+    if comps == 1:
+        if t.dim() != 1 or t.shape[0] != n or (n > 1 and t.stride(0) != 1):
+            raise ValueError(f"{name} must have shape [{n}] with unit stride")
+    else:
+        if t.dim() != 2 or t.shape[0] != comps or t.shape[1] != n or (n > 1 and t.stride(1) != 1):
+            raise ValueError(f"{name} must have shape [{comps}, {n}] with unit stride along n")
+    return t
+
+
+def _ld(t: torch.Tensor, n: int) -> int:
+    return t.stride(0) if t.dim() == 2 else n
+
+
+def _stream(stream):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+def make_opts(*, h0=0.0, h_fixed=0.0, t_end=0.0, max_steps=0, terms=_lib.PN_TERM_ALL,
+              theta_literal=0, schedule="persistent", block=0, waves_per_simd=0,
+              refill_min=0) -> PnOpts:
+    o = PnOpts()
+    o.h0, o.h_fixed, o.t_end = float(h0), float(h_fixed), float(t_end)
+    o.max_steps, o.terms, o.theta_literal = int(max_steps), int(terms), int(theta_literal)
+    o.schedule = SCHEDULES[schedule] if isinstance(schedule, str) else int(schedule)
+    o.block, o.waves_per_simd, o.refill_min = int(block), int(waves_per_simd), int(refill_min)
+    return o
+
+
+def alloc_outputs(n: int, device=None, dots: bool = True) -> dict:
+    dev = device or torch.device("cuda", torch.cuda.current_device())
+    return {
+        "y": torch.empty((10, n), dtype=torch.float64, device=dev),
+        "t": torch.empty((n,), dtype=torch.float64, device=dev),
+        "steps": torch.empty((3, n), dtype=torch.int32, device=dev),
+        "status": torch.empty((n,), dtype=torch.int32, device=dev),
+        "dots": torch.empty((3, n), dtype=torch.float64, device=dev) if dots else None,
+    }
+
+
+def pn_integrate(m, S0, L0, omega0, omega_f, tol, opts: PnOpts | None = None, out=None,
+                 dots: bool = True, stream=None) -> dict:
+    """Integrate every inspiral from omega0 to omega_f (or to opts.t_end).
+
+    m [2, n], S0 [6, n], L0 [3, n], omega0 [n] (float64, on the GPU).
+    Returns dict(y [10, n], t [n], steps [3, n] int32, status [n] int32,
+    dots [3, n] or None).  Asynchronous on the current stream.
+    """
+    n = int(omega0.shape[0])
+    _soa(omega0, 1, n, "omega0")
+    _soa(m, 2, n, "m"); _soa(S0, 6, n, "S0"); _soa(L0, 3, n, "L0")
+    lds = {_ld(m, n), _ld(S0, n), _ld(L0, n)}
+    if out is None:
+        out = alloc_outputs(n, omega0.device, dots)
+    for k, c in (("y", 10), ("steps", 3)):
+        _soa(out[k], c, n, k, torch.int32 if k == "steps" else torch.float64)
+        lds.add(_ld(out[k], n))
+    _soa(out["t"], 1, n, "t"); _soa(out["status"], 1, n, "status", torch.int32)
+    if out.get("dots") is not None:
+        _soa(out["dots"], 3, n, "dots")
+        lds.add(_ld(out["dots"], n))
+    if n > 0 and len(lds) != 1:
+        raise ValueError("all [components, n] arrays must share one leading dimension")
+    ld = lds.pop() if n > 0 else 0
+    o = opts if opts is not None else make_opts()
+    p = lambda t: C.c_void_p(t.data_ptr()) if t is not None else None
+    rc = load().pn_integrate(n, ld, p(m), p(S0), p(L0), p(omega0), float(omega_f), float(tol),
+                             C.byref(o), p(out["y"]), p(out["t"]), p(out["steps"]),
+                             p(out["status"]), p(out.get("dots")), _stream(stream))
+    check(rc, "pn_integrate")
+    return out
+
+
+def pn_rhs(m, y, opts: PnOpts | None = None, stream=None) -> torch.Tensor:
+    """Eqs. (1)-(4) pointwise: m [2, n], y [10, n] -> dy/dt [10, n]."""
+    n = int(y.shape[1])
+    _soa(m, 2, n, "m"); _soa(y, 10, n, "y")
+    if _ld(m, n) != _ld(y, n):
+        raise ValueError("m and y must share one leading dimension")
+    out = torch.empty((10, n), dtype=torch.float64, device=y.device)
+    if _ld(out, n) != _ld(y, n):
+        raise ValueError("y must be contiguous")
+    o = opts if opts is not None else make_opts()
+    rc = load().pn_rhs(n, _ld(y, n), C.c_void_p(m.data_ptr()), C.c_void_p(y.data_ptr()),
+                       C.c_void_p(out.data_ptr()), C.byref(o), _stream(stream))
+    check(rc, "pn_rhs")
+    return out
+
+
+def pn_observables(y, stream=None) -> torch.Tensor:
+    """(S1_hat.S2_hat, S1_hat.L_hat, S2_hat.L_hat) of states y [10, n] -> [3, n]."""
+    n = int(y.shape[1])
+    _soa(y, 10, n, "y")
+    out = torch.empty((3, n), dtype=torch.float64, device=y.device)
+    if _ld(out, n) != _ld(y, n):
+        raise ValueError("y must be contiguous")
+    rc = load().pn_observables(n, _ld(y, n), C.c_void_p(y.data_ptr()), C.c_void_p(out.data_ptr()),
+                               _stream(stream))
+    check(rc, "pn_observables")
+    return out
+
+
+def to_device(pop: dict, device="cuda") -> dict:
+    """The input arrays of a population (numpy, from population.generate) on the GPU."""
+    return {k: torch.from_numpy(pop[k]).to(device) for k in ("m", "S", "L", "omega0")}

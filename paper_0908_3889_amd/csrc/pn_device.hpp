@@ -1,0 +1,242 @@
+// pn_device.hpp -- device-side pieces of the gfx950 integrator: the
+// per-inspiral coefficient row, the right-hand side of Eqs. (1)-(4), and the
+// few FP64 special functions the path needs (cube root, natural log,
+// z^(-1/10)), each built from a hardware FP32 seed and FP64 Newton steps.
+//
+// Every value here is computed by this file; nothing is shared with the CPU
+// oracle.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pn.h"
+
+namespace pn {
+
+// ---------------------------------------------------------------------------
+// FP64 special functions.  Each states the range it accepts; the callers
+// guarantee or clamp it.
+// ---------------------------------------------------------------------------
+
+// cube root of a in [2^-120, 2^120]: FP32 seed from the hardware log2/exp2,
+// then two Newton steps x <- x - (x^3 - a) r with r ~ 1/(3 x0^2) from the FP32
+// reciprocal.  The seed is good to ~3e-7, the first step to ~1e-13, the
+// second to rounding.
+__device__ __forceinline__ double cbrt_mid(double a) {
+    const float af = (float)a;
+    const float x0f = __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(af) * (1.0f / 3.0f));
+    const double r = (double)__builtin_amdgcn_rcpf(3.0f * x0f * x0f);
+    double x = (double)x0f;
+    double t = __builtin_fma(x * x, x, -a);
+    x = __builtin_fma(-t, r, x);
+    t = __builtin_fma(x * x, x, -a);
+    x = __builtin_fma(-t, r, x);
+    return x;
+}
+
+// real cube root of any finite v (negative v gives -cbrt(|v|)).  Magnitudes
+// outside [2^-120, 2^120] are first scaled by 2^(3k) into range; lanes that
+// never see such values skip that branch.
+__device__ __forceinline__ double cbrt_real(double v) {
+    double a = __builtin_fabs(v);
+    int k = 0;
+    if (!(a >= 0x1p-120 && a <= 0x1p120)) {
+        const int e = __builtin_amdgcn_frexp_exp(a);
+        k = (e >= 0 ? e : e - 2) / 3;                      // floor(e/3)
+        a = __builtin_amdgcn_ldexp(a, -3 * k);
+        if (!(a > 0.0) || !__builtin_isfinite(a)) return v;   // 0, inf or NaN
+    }
+    const double x = __builtin_amdgcn_ldexp(cbrt_mid(a), k);
+    return __builtin_copysign(x, v);
+}
+
+// 1/d for d > 0 normal: hardware reciprocal refined by two Newton steps.
+__device__ __forceinline__ double rcp_pos(double d) {
+    double r = __builtin_amdgcn_rcp(d);
+    double e = __builtin_fma(-d, r, 1.0);
+    r = __builtin_fma(r, e, r);
+    e = __builtin_fma(-d, r, 1.0);
+    return __builtin_fma(r, e, r);
+}
+
+// natural log of v > 0 (normal or subnormal): v = 2^e m with m in [sqrt(1/2), sqrt(2)),
+// ln m = 2 atanh(s), s = (m-1)/(m+1), |s| <= 0.1716, by its Taylor series
+// sum_k s^(2k+1)/(2k+1) truncated after s^19 (relative remainder < 3e-17).
+__device__ __forceinline__ double log_pos(double v) {
+    double m = __builtin_amdgcn_frexp_mant(v);          // [0.5, 1)
+    int e = __builtin_amdgcn_frexp_exp(v);
+    const bool lo = m < 0.70710678118654752440;
+    m = lo ? m * 2.0 : m;
+    e = lo ? e - 1 : e;
+    const double num = m - 1.0;                          // exact (Sterbenz)
+    const double den = m + 1.0;
+    const double rden = rcp_pos(den);
+    double s = num * rden;
+    s = __builtin_fma(__builtin_fma(-s, den, num), rden, s);   // one residual correction
+    const double s2 = s * s;
+    double p = 1.0 / 19.0;
+    p = __builtin_fma(p, s2, 1.0 / 17.0);
+    p = __builtin_fma(p, s2, 1.0 / 15.0);
+    p = __builtin_fma(p, s2, 1.0 / 13.0);
+    p = __builtin_fma(p, s2, 1.0 / 11.0);
+    p = __builtin_fma(p, s2, 1.0 / 9.0);
+    p = __builtin_fma(p, s2, 1.0 / 7.0);
+    p = __builtin_fma(p, s2, 1.0 / 5.0);
+    p = __builtin_fma(p, s2, 1.0 / 3.0);
+    const double lnm = __builtin_fma(2.0 * s * s2, p, 2.0 * s);
+    // ln 2 split so that e * LN2_HI is exact for |e| < 2^11
+    const double LN2_HI = 6.93147180369123816490e-01;
+    const double LN2_LO = 1.90821492927058770002e-10;
+    const double de = (double)e;
+    return __builtin_fma(de, LN2_HI, __builtin_fma(de, LN2_LO, lnm));
+}
+
+// z^(-1/10) for z in [2^-30, 2^30] (callers clamp): FP32 seed, then two Newton
+// steps of y <- y (11 - z y^10) / 10, each squaring the relative error
+// (times 5.5).
+__device__ __forceinline__ double pow_m_tenth(double z) {
+    const float zf = (float)z;
+    double y = (double)__builtin_amdgcn_exp2f(__builtin_amdgcn_logf(zf) * -0.1f);
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+        const double y2 = y * y;
+        const double y5 = (y2 * y2) * y;
+        const double t = __builtin_fma(-z, y5 * y5, 11.0);
+        y = (y * t) * 0.1;
+    }
+    return y;
+}
+
+// ---------------------------------------------------------------------------
+// Per-inspiral coefficient row: everything in Eqs. (1)-(4) that depends only
+// on (m1, m2) and the term switches.  Built once per inspiral.
+// ---------------------------------------------------------------------------
+struct Row {
+    double M;      // m1 + m2
+    double c2;     // -(743 + 924 eta)/336                                (M w)^{2/3}
+    double so1;    // (113 m1^2/M^2 + 75 eta)/(12 m1^2)  [times L.S1]     (M w)^{1}
+    double so2;    // (113 m2^2/M^2 + 75 eta)/(12 m2^2)  [times L.S2]
+    double c4;     // 34103/18144 + 13661/2016 eta + 59/18 eta^2          (M w)^{4/3}
+    double ss1;    // 247 eta / (48 m1^2 m2^2)            [times S1.S2]
+    double ss2;    // 721 eta / (48 m1^2 m2^2)            [times L.S1 L.S2]
+    double c5;     // -(4159 + 15876 eta) pi / 672                        (M w)^{5/3}
+    double c6;     // 3PN constant part, -(856/105) ln 16 included        (M w)^{2}
+    double c7;     // (-4415/4032 + 358675/6048 eta + 91495/1512 eta^2) pi (M w)^{7/3}
+    double K;      // (96/5) eta / M^2: d omega/dt = K (M w)^2 x^5 {...}
+    double hinvM;  // 1/(2M)
+    double g1;     // eta (4 + 3 m2/m1)
+    double g2;     // eta (4 + 3 m1/m2)
+    double sig;    // 1/M^2
+    double lam;    // 1/(eta M^2)
+};
+
+// Launch-uniform switches folded into numbers: 4 pi and -1712/105 when the
+// non-spinning PN terms are on, else 0.
+struct TermConsts {
+    double c3;     // 4 pi
+    double c6log;  // coefficient of ln x, x = (M w)^{1/3}: -(856/105) * 2
+};
+
+#define PN_PI 3.14159265358979323846
+#define PN_GAMMA_E 0.57721566490153286061
+#define PN_LN16 2.77258872223978123767
+
+__device__ __forceinline__ Row make_row(double m1, double m2, int terms, int theta_literal) {
+    Row r;
+    const double M = m1 + m2;
+    const double iM = 1.0 / M;
+    const double eta = m1 * m2 * iM * iM;
+    const double pn = (terms & PN_TERM_PN) ? 1.0 : 0.0;
+    const double fso = (terms & PN_TERM_SO_WDOT) ? 1.0 : 0.0;
+    const double fss = (terms & PN_TERM_SS_WDOT) ? 1.0 : 0.0;
+    r.M = M;
+    r.c2 = pn * (-(743.0 + 924.0 * eta) / 336.0);
+    r.so1 = fso * (113.0 * m1 * m1 * iM * iM + 75.0 * eta) / (12.0 * m1 * m1);
+    r.so2 = fso * (113.0 * m2 * m2 * iM * iM + 75.0 * eta) / (12.0 * m2 * m2);
+    r.c4 = pn * (34103.0 / 18144.0 + (13661.0 / 2016.0) * eta + (59.0 / 18.0) * eta * eta);
+    const double ssd = eta / (48.0 * m1 * m1 * m2 * m2);
+    r.ss1 = fss * 247.0 * ssd;
+    r.ss2 = fss * 721.0 * ssd;
+    r.c5 = pn * (-(4159.0 + 15876.0 * eta) * PN_PI / 672.0);
+    // 3PN: theta_hat = 1039/4620 multiplies eta once (the expansion of
+    // Eq. (1)'s source), or, with theta_literal, eta^2 as printed.
+    const double theta_term = (88.0 / 3.0) * (1039.0 / 4620.0) * (theta_literal ? eta : 1.0);
+    r.c6 = pn * ((16447322263.0 / 139708800.0) - (1712.0 / 105.0) * PN_GAMMA_E
+                 + (16.0 / 3.0) * PN_PI * PN_PI
+                 + (-273811877.0 / 1088640.0 + (451.0 / 48.0) * PN_PI * PN_PI - theta_term) * eta
+                 + (541.0 / 896.0) * eta * eta - (5605.0 / 2592.0) * eta * eta * eta
+                 - (856.0 / 105.0) * PN_LN16);
+    r.c7 = pn * ((-4415.0 / 4032.0 + (358675.0 / 6048.0) * eta + (91495.0 / 1512.0) * eta * eta) * PN_PI);
+    r.K = (terms & PN_TERM_RR) ? (96.0 / 5.0) * eta * iM * iM : 0.0;
+    r.hinvM = 0.5 * iM;
+    r.g1 = (terms & PN_TERM_SO_PREC) ? eta * (4.0 + 3.0 * m2 / m1) : 0.0;
+    r.g2 = (terms & PN_TERM_SO_PREC) ? eta * (4.0 + 3.0 * m1 / m2) : 0.0;
+    r.sig = (terms & PN_TERM_SS_PREC) ? iM * iM : 0.0;
+    r.lam = 1.0 / (eta * M * M);
+    return r;
+}
+
+// dy/dt of Eqs. (1)-(4) at y = (w, S1, S2, L).  Returns d omega/dt in d[0].
+//
+// With v = M w and x = v^{1/3}:
+//   d w/dt = K v^2 x^5 B,  B = 1 + x^2 (c2 + x (c3' + x (c4' + x (c5 + x (c6' + x c7)))))
+//     c3' = 4 pi - so1 L.S1 - so2 L.S2,  c4' = c4 - ss1 S1.S2 + ss2 (L.S1)(L.S2),
+//     c6' = c6 - (1712/105) ln x;
+//   Omega_1 x S1 = p [ (g1 x^2 - 3 sig v L.S2) (L x S1) - sig v (S1 x S2) ],
+//   Omega_2 x S2 = p [ (g2 x^2 - 3 sig v L.S1) (L x S2) + sig v (S1 x S2) ],
+//     p = v/(2M) (Eq. (4) expanded; (M w)^2 (M w)^{-1/3} / (2M) = p x^2);
+//   dL/dt = -lam x (dS1/dt + dS2/dt)   (Eq. (3)).
+// Off the physical region (stage points of rejected or fixed steps) omega may
+// be negative; x is then the real cube root and the log term uses
+// ln(16 x^2) = ln 16 + (2/3) ln|v|, which is what Eq. (1) gives for any real x.
+__device__ __forceinline__ void rhs(const Row& r, const TermConsts& tc, const double* __restrict__ y,
+                                    double* __restrict__ d) {
+    const double v = r.M * y[0];
+    const double x = cbrt_real(v);
+    const double lnx = log_pos(__builtin_fabs(v)) * (1.0 / 3.0);
+    const double x2 = x * x;
+    const double L0 = y[7], L1 = y[8], L2 = y[9];
+    const double a0 = y[1], a1 = y[2], a2 = y[3];   // S1
+    const double b0 = y[4], b1 = y[5], b2 = y[6];   // S2
+    const double LS1 = __builtin_fma(L0, a0, __builtin_fma(L1, a1, L2 * a2));
+    const double LS2 = __builtin_fma(L0, b0, __builtin_fma(L1, b1, L2 * b2));
+    const double S12 = __builtin_fma(a0, b0, __builtin_fma(a1, b1, a2 * b2));
+
+    const double c3p = __builtin_fma(-r.so2, LS2, __builtin_fma(-r.so1, LS1, tc.c3));
+    const double c4p = __builtin_fma(r.ss2 * LS1, LS2, __builtin_fma(-r.ss1, S12, r.c4));
+    const double c6p = __builtin_fma(tc.c6log, lnx, r.c6);
+    double B = __builtin_fma(x, r.c7, c6p);
+    B = __builtin_fma(x, B, r.c5);
+    B = __builtin_fma(x, B, c4p);
+    B = __builtin_fma(x, B, c3p);
+    B = __builtin_fma(x, B, r.c2);
+    B = __builtin_fma(x2, B, 1.0);
+    const double x5 = x2 * x2 * x;
+    d[0] = (r.K * (v * v)) * x5 * B;
+
+    const double p = v * r.hinvM;
+    const double sv = r.sig * v;
+    const double al1 = p * __builtin_fma(r.g1, x2, -3.0 * sv * LS2);
+    const double al2 = p * __builtin_fma(r.g2, x2, -3.0 * sv * LS1);
+    const double be = p * sv;
+    // L x S1, L x S2, S1 x S2
+    const double u0 = __builtin_fma(L1, a2, -L2 * a1), u1 = __builtin_fma(L2, a0, -L0 * a2),
+                 u2 = __builtin_fma(L0, a1, -L1 * a0);
+    const double w0 = __builtin_fma(L1, b2, -L2 * b1), w1 = __builtin_fma(L2, b0, -L0 * b2),
+                 w2 = __builtin_fma(L0, b1, -L1 * b0);
+    const double c0 = __builtin_fma(a1, b2, -a2 * b1), c1 = __builtin_fma(a2, b0, -a0 * b2),
+                 cc2 = __builtin_fma(a0, b1, -a1 * b0);
+    d[1] = __builtin_fma(al1, u0, -be * c0);
+    d[2] = __builtin_fma(al1, u1, -be * c1);
+    d[3] = __builtin_fma(al1, u2, -be * cc2);
+    d[4] = __builtin_fma(al2, w0, be * c0);
+    d[5] = __builtin_fma(al2, w1, be * c1);
+    d[6] = __builtin_fma(al2, w2, be * cc2);
+    const double q = -r.lam * x;
+    d[7] = q * (d[1] + d[4]);
+    d[8] = q * (d[2] + d[5]);
+    d[9] = q * (d[3] + d[6]);
+}
+
+}  // namespace pn

@@ -1,0 +1,581 @@
+// pn_lib.hip -- gfx950 kernels and the C interface declared in include/pn.h.
+//
+// The hot path: one inspiral per lane, its state, stage vectors and
+// coefficient row in registers; adaptive Dormand-Prince RK5(4) with FSAL
+// (Sec. II: Dormand-Prince, tolerance, h = 10); termination at omega_f by a
+// last stretch integrated with omega as the independent variable; a
+// persistent grid in which a wave hands new inspirals to its idle lanes
+// (ballot + one atomic add per wave) so that inspirals of very different
+// lengths share lanes without leaving them idle.
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "pn.h"
+#include "pn_device.hpp"
+
+namespace pn {
+
+// ---------------------------------------------------------------------------
+// Dormand-Prince RK5(4)7M tableau (Dormand & Prince 1980)
+// ---------------------------------------------------------------------------
+constexpr double A21 = 1.0 / 5.0;
+constexpr double A31 = 3.0 / 40.0, A32 = 9.0 / 40.0;
+constexpr double A41 = 44.0 / 45.0, A42 = -56.0 / 15.0, A43 = 32.0 / 9.0;
+constexpr double A51 = 19372.0 / 6561.0, A52 = -25360.0 / 2187.0, A53 = 64448.0 / 6561.0,
+                 A54 = -212.0 / 729.0;
+constexpr double A61 = 9017.0 / 3168.0, A62 = -355.0 / 33.0, A63 = 46732.0 / 5247.0,
+                 A64 = 49.0 / 176.0, A65 = -5103.0 / 18656.0;
+// 5th-order weights (= stage-7 row, FSAL); b2 = b7 = 0
+constexpr double B1 = 35.0 / 384.0, B3 = 500.0 / 1113.0, B4 = 125.0 / 192.0,
+                 B5 = -2187.0 / 6784.0, B6 = 11.0 / 84.0;
+// error weights e = b - bhat; e2 = 0
+constexpr double E1 = 71.0 / 57600.0, E3 = -71.0 / 16695.0, E4 = 71.0 / 1920.0,
+                 E5 = -17253.0 / 339200.0, E6 = 22.0 / 525.0, E7 = -1.0 / 40.0;
+
+// accept when err = sqrt(z) <= 1, i.e. z <= 1 + 2^-52 (sqrt rounds that to 1)
+constexpr double Z_ACCEPT = 1.0 + 2.220446049250313e-16;
+
+struct Uni {
+    double omega_f, tol, h0, h_fixed, t_end;
+    TermConsts tc;
+    int64_t n, ld, max_steps;
+    int terms, theta_literal;
+    int fixed, tend;
+    int refill_min;
+    int rr_on;
+};
+
+struct Io {
+    const double* __restrict__ m;
+    const double* __restrict__ S0;
+    const double* __restrict__ L0;
+    const double* __restrict__ w0;
+    double* __restrict__ y;
+    double* __restrict__ t;
+    int32_t* __restrict__ steps;
+    int32_t* __restrict__ status;
+    double* __restrict__ dots;
+};
+
+// Everything one lane carries for its current inspiral.
+struct Lane {
+    double y[10];
+    double k1[10];
+    double dt1;       // dt/d(variable) of k1: 1 in time mode, 1/omega-dot in omega mode
+    double t, h;
+    Row row;
+    int64_t idx;
+    int acc, rej, nrhs;
+    bool omega_mode, last_rej;
+};
+
+__device__ __forceinline__ bool finite(double v) { return __builtin_isfinite(v); }
+
+// omega-mode: divide the RHS by omega-dot and put 1 in the omega slot.
+__device__ __forceinline__ void to_omega_variable(double* k, double& dt, bool om) {
+    const double s = om ? 1.0 / k[0] : 1.0;
+#pragma unroll
+    for (int c = 1; c < 10; ++c) k[c] *= s;
+    k[0] = om ? 1.0 : k[0];
+    dt = s;
+}
+
+__device__ void write_out(const Io& io, const Uni& u, const Lane& L, int st) {
+    const int64_t i = L.idx, ld = u.ld;
+#pragma unroll
+    for (int c = 0; c < 10; ++c) io.y[c * ld + i] = L.y[c];
+    io.t[i] = L.t;
+    io.steps[i] = L.acc;
+    io.steps[ld + i] = L.rej;
+    io.steps[2 * ld + i] = L.nrhs;
+    io.status[i] = st;
+    if (io.dots) {
+        const double* y = L.y;
+        const double n1 = __builtin_sqrt(y[1] * y[1] + y[2] * y[2] + y[3] * y[3]);
+        const double n2 = __builtin_sqrt(y[4] * y[4] + y[5] * y[5] + y[6] * y[6]);
+        const double nl = __builtin_sqrt(y[7] * y[7] + y[8] * y[8] + y[9] * y[9]);
+        const double s12 = y[1] * y[4] + y[2] * y[5] + y[3] * y[6];
+        const double s1l = y[1] * y[7] + y[2] * y[8] + y[3] * y[9];
+        const double s2l = y[4] * y[7] + y[5] * y[8] + y[6] * y[9];
+        io.dots[i] = (n1 > 0.0 && n2 > 0.0) ? s12 / (n1 * n2) : 0.0;
+        io.dots[ld + i] = (n1 > 0.0 && nl > 0.0) ? s1l / (n1 * nl) : 0.0;
+        io.dots[2 * ld + i] = (n2 > 0.0 && nl > 0.0) ? s2l / (n2 * nl) : 0.0;
+    }
+}
+
+// Load inspiral idx into the lane and evaluate k1.  Returns 0 when the lane
+// now integrates it, or a status when it is finished at once (bad input, or
+// omega0 >= omega_f), in which case the outputs are already written.
+__device__ int load_lane(const Io& io, const Uni& u, Lane& L, int64_t idx) {
+    const int64_t ld = u.ld;
+    L.idx = idx;
+    const double m1 = io.m[idx], m2 = io.m[ld + idx];
+    L.y[0] = io.w0[idx];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) L.y[1 + c] = io.S0[c * ld + idx];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) L.y[7 + c] = io.L0[c * ld + idx];
+    L.t = 0.0;
+    L.acc = 0; L.rej = 0; L.nrhs = 0;
+    L.omega_mode = false; L.last_rej = false;
+    L.h = u.fixed ? u.h_fixed : u.h0;
+    bool bad = !(m1 > 0.0) || !(m2 > 0.0) || !(L.y[0] > 0.0) || !finite(m1) || !finite(m2);
+#pragma unroll
+    for (int c = 0; c < 10; ++c) bad = bad || !finite(L.y[c]);
+    if (bad) { write_out(io, u, L, PN_ST_BAD_INPUT); return PN_ST_BAD_INPUT; }
+    if (!u.tend && !(L.y[0] < u.omega_f)) { write_out(io, u, L, PN_ST_DONE_AT_START); return PN_ST_DONE_AT_START; }
+    L.row = make_row(m1, m2, u.terms, u.theta_literal);
+    rhs(L.row, u.tc, L.y, L.k1);
+    L.dt1 = 1.0;
+    L.nrhs = 1;
+    return 0;
+}
+
+// One attempted Dormand-Prince step of an active lane.  Returns 0 while the
+// inspiral continues, 1 when it ended normally (PN_ST_OK), or a negative
+// status.  `any_w` is true when some lane of the wave is in omega mode.
+__device__ __forceinline__ int step_lane(const Uni& u, Lane& L, bool any_w) {
+    // guards at the start of a step
+    if (L.acc + L.rej >= u.max_steps) return PN_ST_MAX_STEPS;
+    if (!L.omega_mode && u.rr_on && L.k1[0] <= 0.0) return PN_ST_OMEGADOT_NONPOSITIVE;
+    if (L.omega_mode && L.dt1 <= 0.0) return PN_ST_OMEGADOT_NONPOSITIVE;
+
+    double htry = L.h;
+    bool last = false;
+    if (L.omega_mode) {
+        const double remain = u.omega_f - L.y[0];
+        if (htry >= remain) { htry = remain; last = true; }
+    } else if (u.tend) {
+        const double remain = u.t_end - L.t;
+        if (htry >= remain) { htry = remain; last = true; }
+    }
+
+    const Row& R = L.row;
+    const double* y = L.y;
+    const double* k1 = L.k1;
+    double Y[10], k2[10], k3[10], k4[10], k5[10], k6[10];
+    double dt2, dt3, dt4, dt5, dt6, dt7;
+
+    const double h = htry;
+    {
+        const double c1 = h * A21;
+#pragma unroll
+        for (int c = 0; c < 10; ++c) Y[c] = __builtin_fma(c1, k1[c], y[c]);
+        rhs(R, u.tc, Y, k2);
+        if (any_w) to_omega_variable(k2, dt2, L.omega_mode); else dt2 = 1.0;
+    }
+    {
+        const double c1 = h * A31, c2 = h * A32;
+#pragma unroll
+        for (int c = 0; c < 10; ++c) Y[c] = __builtin_fma(c2, k2[c], __builtin_fma(c1, k1[c], y[c]));
+        rhs(R, u.tc, Y, k3);
+        if (any_w) to_omega_variable(k3, dt3, L.omega_mode); else dt3 = 1.0;
+    }
+    {
+        const double c1 = h * A41, c2 = h * A42, c3 = h * A43;
+#pragma unroll
+        for (int c = 0; c < 10; ++c)
+            Y[c] = __builtin_fma(c3, k3[c], __builtin_fma(c2, k2[c], __builtin_fma(c1, k1[c], y[c])));
+        rhs(R, u.tc, Y, k4);
+        if (any_w) to_omega_variable(k4, dt4, L.omega_mode); else dt4 = 1.0;
+    }
+    {
+        const double c1 = h * A51, c2 = h * A52, c3 = h * A53, c4 = h * A54;
+#pragma unroll
+        for (int c = 0; c < 10; ++c)
+            Y[c] = __builtin_fma(c4, k4[c], __builtin_fma(c3, k3[c],
+                   __builtin_fma(c2, k2[c], __builtin_fma(c1, k1[c], y[c]))));
+        rhs(R, u.tc, Y, k5);
+        if (any_w) to_omega_variable(k5, dt5, L.omega_mode); else dt5 = 1.0;
+    }
+    {
+        const double c1 = h * A61, c2 = h * A62, c3 = h * A63, c4 = h * A64, c5 = h * A65;
+#pragma unroll
+        for (int c = 0; c < 10; ++c)
+            Y[c] = __builtin_fma(c5, k5[c], __builtin_fma(c4, k4[c], __builtin_fma(c3, k3[c],
+                   __builtin_fma(c2, k2[c], __builtin_fma(c1, k1[c], y[c])))));
+        rhs(R, u.tc, Y, k6);
+        if (any_w) to_omega_variable(k6, dt6, L.omega_mode); else dt6 = 1.0;
+    }
+    // stage 7 point = 5th-order solution; the error sum over k1, k3..k6 is
+    // formed now so that those vectors die before the last RHS
+    double Ep[10];
+    {
+        const double c1 = h * B1, c3 = h * B3, c4 = h * B4, c5 = h * B5, c6 = h * B6;
+#pragma unroll
+        for (int c = 0; c < 10; ++c) {
+            Y[c] = __builtin_fma(c6, k6[c], __builtin_fma(c5, k5[c], __builtin_fma(c4, k4[c],
+                   __builtin_fma(c3, k3[c], __builtin_fma(c1, k1[c], y[c])))));
+            Ep[c] = __builtin_fma(E6, k6[c], __builtin_fma(E5, k5[c], __builtin_fma(E4, k4[c],
+                    __builtin_fma(E3, k3[c], E1 * k1[c]))));
+        }
+    }
+    double k7[10];
+    rhs(R, u.tc, Y, k7);
+    if (any_w) to_omega_variable(k7, dt7, L.omega_mode); else dt7 = 1.0;
+    L.nrhs += 6;
+
+    // error norm: z = err^2 = mean_c (e_c / (tol + tol max(|y_c|, |y5_c|)))^2
+    double z = 0.0;
+    bool fin = true;
+    if (!u.fixed) {
+#pragma unroll
+        for (int c = 0; c < 10; ++c) {
+            const double e = h * __builtin_fma(E7, k7[c], Ep[c]);
+            const double sc = __builtin_fma(u.tol, __builtin_fmax(__builtin_fabs(y[c]), __builtin_fabs(Y[c])), u.tol);
+            const double q = e * rcp_pos(sc);
+            z = __builtin_fma(q, q, z);
+        }
+        z *= 0.1;
+        fin = !__builtin_isnan(z);
+    }
+#pragma unroll
+    for (int c = 0; c < 10; ++c) fin = fin && finite(Y[c]);
+    if (!fin) return PN_ST_NONFINITE;
+
+    if (u.fixed || z <= Z_ACCEPT) {
+        if (!L.omega_mode && !u.tend && Y[0] > u.omega_f) {
+            // the candidate passes omega_f: discard it and finish the stretch
+            // with omega as the independent variable
+            L.omega_mode = true;
+            const double s = 1.0 / L.k1[0];
+#pragma unroll
+            for (int c = 1; c < 10; ++c) L.k1[c] *= s;
+            L.k1[0] = 1.0;
+            L.dt1 = s;
+            L.h = u.omega_f - L.y[0];
+            L.last_rej = false;
+            return 0;
+        }
+        if (L.omega_mode) {
+            const double dts = B1 * L.dt1 + B3 * dt3 + B4 * dt4 + B5 * dt5 + B6 * dt6;
+            L.t = __builtin_fma(h, dts, L.t);
+        } else {
+            L.t += h;
+        }
+#pragma unroll
+        for (int c = 0; c < 10; ++c) { L.y[c] = Y[c]; L.k1[c] = k7[c]; }
+        L.dt1 = dt7;
+        L.acc += 1;
+        if (!L.omega_mode && !u.tend && L.y[0] == u.omega_f) last = true;
+        if (last) {
+            if (L.omega_mode) L.y[0] = u.omega_f;
+            return 1;
+        }
+        if (!u.fixed) {
+            const double zc = __builtin_fmin(__builtin_fmax(z, 9.313225746154785e-10), 1.073741824e9);
+            double fac = 0.9 * pow_m_tenth(zc);
+            fac = __builtin_fmin(5.0, __builtin_fmax(0.2, fac));
+            if (L.last_rej) fac = __builtin_fmin(fac, 1.0);
+            L.h = h * fac;
+            L.last_rej = false;
+        }
+        (void)dt2;
+        return 0;
+    }
+    // rejected
+    L.rej += 1;
+    const double zc = __builtin_fmin(z, 1.073741824e9);
+    const double fac = __builtin_fmax(0.2, 0.9 * pow_m_tenth(zc));
+    L.h = h * fac;
+    L.last_rej = true;
+    const double scale = L.omega_mode ? __builtin_fabs(L.y[0]) : __builtin_fmax(1.0, __builtin_fabs(L.t));
+    if (L.h < 1e-14 * scale) return PN_ST_H_UNDERFLOW;
+    return 0;
+}
+
+__device__ __forceinline__ int lane_id() { return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u)); }
+
+__device__ __forceinline__ uint64_t wave_ballot(bool p) { return __ballot(p); }
+
+// Persistent kernel: each wave loops, handing new inspirals to idle lanes
+// from a global counter, until the counter passes n and its lanes are done.
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void integrate_persistent(Io io, Uni u, unsigned long long* counter) {
+    const int lane = lane_id();
+    Lane L;
+    L.idx = -1;
+    bool active = false;
+    bool exhausted = false;     // wave-uniform
+    for (;;) {
+        // ---- refill idle lanes --------------------------------------------------
+        if (!exhausted) {
+            uint64_t need = wave_ballot(!active);
+            const int nactive = 64 - __popcll(need);
+            if (need != 0 && (__popcll(need) >= u.refill_min || nactive == 0)) {
+                while (need != 0 && !exhausted) {
+                    const int cnt = __popcll(need);
+                    const int leader = __ffsll((unsigned long long)need) - 1;
+                    unsigned long long base = 0;
+                    if (lane == leader) base = atomicAdd(counter, (unsigned long long)cnt);
+                    const unsigned lo = __builtin_amdgcn_readlane((unsigned)(base & 0xffffffffu), leader);
+                    const unsigned hi = __builtin_amdgcn_readlane((unsigned)(base >> 32), leader);
+                    base = ((unsigned long long)hi << 32) | lo;
+                    bool still = false;
+                    if (!active) {
+                        const unsigned rank = __builtin_amdgcn_mbcnt_hi((unsigned)(need >> 32),
+                                              __builtin_amdgcn_mbcnt_lo((unsigned)need, 0u));
+                        const unsigned long long idx = base + rank;
+                        if (idx < (unsigned long long)u.n) {
+                            const int st = load_lane(io, u, L, (int64_t)idx);
+                            if (st == 0) active = true; else still = true;
+                        }
+                    }
+                    if (base + cnt >= (unsigned long long)u.n) exhausted = true;
+                    need = wave_ballot(still);
+                }
+            }
+        }
+        if (wave_ballot(active) == 0) {
+            if (exhausted) break;
+            continue;
+        }
+        // ---- one step on every active lane ----------------------------------------
+        const bool any_w = wave_ballot(active && L.omega_mode) != 0;
+        if (active) {
+            const int r = step_lane(u, L, any_w);
+            if (r != 0) {
+                write_out(io, u, L, r == 1 ? PN_ST_OK : r);
+                active = false;
+            }
+        }
+    }
+}
+
+// One lane per inspiral, no refill: a wave runs until its longest inspiral ends.
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void integrate_static(Io io, Uni u) {
+    const int64_t idx = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    Lane L;
+    bool active = false;
+    if (idx < u.n) active = load_lane(io, u, L, idx) == 0;
+    for (;;) {
+        if (wave_ballot(active) == 0) break;
+        const bool any_w = wave_ballot(active && L.omega_mode) != 0;
+        if (active) {
+            const int r = step_lane(u, L, any_w);
+            if (r != 0) {
+                write_out(io, u, L, r == 1 ? PN_ST_OK : r);
+                active = false;
+            }
+        }
+    }
+}
+
+__global__ void reset_counter(unsigned long long* c) { *c = 0ull; }
+
+__global__ void rhs_kernel(int64_t n, int64_t ld, const double* __restrict__ m, const double* __restrict__ y,
+                           double* __restrict__ d, int terms, int theta_literal, TermConsts tc) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const Row r = make_row(m[i], m[ld + i], terms, theta_literal);
+    double yy[10], dd[10];
+#pragma unroll
+    for (int c = 0; c < 10; ++c) yy[c] = y[c * ld + i];
+    rhs(r, tc, yy, dd);
+#pragma unroll
+    for (int c = 0; c < 10; ++c) d[c * ld + i] = dd[c];
+}
+
+__global__ void observables_kernel(int64_t n, int64_t ld, const double* __restrict__ y, double* __restrict__ dots) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double v[10];
+#pragma unroll
+    for (int c = 0; c < 10; ++c) v[c] = y[c * ld + i];
+    const double n1 = __builtin_sqrt(v[1] * v[1] + v[2] * v[2] + v[3] * v[3]);
+    const double n2 = __builtin_sqrt(v[4] * v[4] + v[5] * v[5] + v[6] * v[6]);
+    const double nl = __builtin_sqrt(v[7] * v[7] + v[8] * v[8] + v[9] * v[9]);
+    const double s12 = v[1] * v[4] + v[2] * v[5] + v[3] * v[6];
+    const double s1l = v[1] * v[7] + v[2] * v[8] + v[3] * v[9];
+    const double s2l = v[4] * v[7] + v[5] * v[8] + v[6] * v[9];
+    dots[i] = (n1 > 0.0 && n2 > 0.0) ? s12 / (n1 * n2) : 0.0;
+    dots[ld + i] = (n1 > 0.0 && nl > 0.0) ? s1l / (n1 * nl) : 0.0;
+    dots[2 * ld + i] = (n2 > 0.0 && nl > 0.0) ? s2l / (n2 * nl) : 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// Host side: per-device context, argument checks, launches
+// ---------------------------------------------------------------------------
+
+constexpr int kCounterSlots = 1024;
+
+struct DevCtx {
+    bool ready = false;
+    int cus = 0;
+    unsigned long long* counters = nullptr;   // kCounterSlots work counters
+    std::atomic<unsigned> next{0};
+};
+
+constexpr int kMaxDevices = 64;
+DevCtx g_ctx[kMaxDevices];
+std::mutex g_ctx_mu;
+
+int get_ctx(DevCtx** out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return PN_ENODEV;
+    DevCtx& c = g_ctx[dev];
+    if (!c.ready) {
+        std::lock_guard<std::mutex> lk(g_ctx_mu);
+        if (!c.ready) {
+            hipDeviceProp_t prop;
+            if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return PN_ENODEV;
+            if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return PN_ENODEV;
+            c.cus = prop.multiProcessorCount;
+            void* p = nullptr;
+            if (hipMalloc(&p, sizeof(unsigned long long) * kCounterSlots) != hipSuccess) return PN_ENOMEM;
+            c.counters = (unsigned long long*)p;
+            c.ready = true;
+        }
+    }
+    *out = &c;
+    return PN_OK;
+}
+
+TermConsts term_consts(int terms) {
+    TermConsts tc;
+    const bool pn_on = (terms & PN_TERM_PN) != 0;
+    tc.c3 = pn_on ? 4.0 * PN_PI : 0.0;
+    tc.c6log = pn_on ? -(1712.0 / 105.0) : 0.0;
+    return tc;
+}
+
+template <int BLOCK>
+hipError_t launch_forward(const Io& io, const Uni& u, int schedule, int waves_per_simd, int cus,
+                          unsigned long long* counter, hipStream_t s) {
+    if (schedule == PN_SCHED_STATIC) {
+        const int64_t grid = (u.n + BLOCK - 1) / BLOCK;
+        hipLaunchKernelGGL(integrate_static<BLOCK>, dim3((unsigned)grid), dim3(BLOCK), 0, s, io, u);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL(reset_counter, dim3(1), dim3(1), 0, s, counter);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t waves_needed = (u.n + 63) / 64;
+    int64_t waves = (int64_t)cus * 4 * waves_per_simd;
+    if (waves > waves_needed) waves = waves_needed;
+    const int64_t grid = (waves * 64 + BLOCK - 1) / BLOCK;
+    hipLaunchKernelGGL(integrate_persistent<BLOCK>, dim3((unsigned)grid), dim3(BLOCK), 0, s, io, u, counter);
+    return hipGetLastError();
+}
+
+}  // namespace pn
+
+using namespace pn;
+
+extern "C" {
+
+const char* pn_strerror(int code) {
+    switch (code) {
+        case PN_OK: return "PN_OK: success";
+        case PN_EINVAL: return "PN_EINVAL: invalid argument";
+        case PN_ENODEV: return "PN_ENODEV: no usable gfx950 device is current";
+        case PN_EHIP: return "PN_EHIP: a HIP runtime call or kernel launch failed";
+        case PN_ENOMEM: return "PN_ENOMEM: device context allocation failed";
+        default: return "unknown pn error code";
+    }
+}
+
+const char* pn_version(void) { return "pn-gfx950 0.1"; }
+
+int pn_integrate(int64_t n, int64_t ld, const double* m, const double* S0, const double* L0,
+                 const double* omega0, double omega_f, double tol, const pn_opts* opt,
+                 double* y_final, double* t_final, int32_t* steps, int32_t* status, double* dots,
+                 void* stream) {
+    pn_opts o;
+    std::memset(&o, 0, sizeof(o));
+    if (opt) o = *opt;
+    if (n < 0 || ld < n) return PN_EINVAL;
+    if (n > 0 && (!m || !S0 || !L0 || !omega0 || !y_final || !t_final || !steps || !status)) return PN_EINVAL;
+    const bool fixed = o.h_fixed > 0.0;
+    const bool tend = o.t_end > 0.0;
+    if (o.h_fixed < 0.0 || !(o.h_fixed == o.h_fixed) || !(o.t_end == o.t_end) || o.t_end < 0.0) return PN_EINVAL;
+    if (!fixed && !(tol > 0.0 && tol < 1e300)) return PN_EINVAL;
+    if (!tend && !(omega_f > 0.0 && omega_f < 1e300)) return PN_EINVAL;
+    if (tend && !(o.t_end < 1e300)) return PN_EINVAL;
+    if (!(o.h0 == o.h0) || o.h0 >= 1e300) return PN_EINVAL;
+    if (o.schedule != PN_SCHED_PERSISTENT && o.schedule != PN_SCHED_STATIC) return PN_EINVAL;
+    const int block = o.block ? o.block : 256;
+    if (block != 64 && block != 128 && block != 256 && block != 512 && block != 1024) return PN_EINVAL;
+    const int wps = o.waves_per_simd ? o.waves_per_simd : 2;
+    if (wps < 1 || wps > 8) return PN_EINVAL;
+    const int refill = o.refill_min ? o.refill_min : 1;
+    if (refill < 1 || refill > 64) return PN_EINVAL;
+    if (o.terms < 0 || o.terms > PN_TERM_ALL) return PN_EINVAL;
+    if (o.theta_literal != 0 && o.theta_literal != 1) return PN_EINVAL;
+    if (n == 0) return PN_OK;
+
+    DevCtx* ctx = nullptr;
+    int rc = get_ctx(&ctx);
+    if (rc != PN_OK) return rc;
+
+    Uni u;
+    u.omega_f = tend ? 0.0 : omega_f;
+    u.tol = fixed ? 1.0 : tol;
+    u.h0 = o.h0 > 0.0 ? o.h0 : 10.0;
+    u.h_fixed = o.h_fixed;
+    u.t_end = o.t_end;
+    u.terms = o.terms > 0 ? o.terms : PN_TERM_ALL;
+    u.theta_literal = o.theta_literal;
+    u.tc = term_consts(u.terms);
+    u.n = n;
+    u.ld = ld;
+    u.max_steps = o.max_steps > 0 ? o.max_steps : 10000000LL;
+    u.fixed = fixed;
+    u.tend = tend;
+    u.refill_min = refill;
+    u.rr_on = (u.terms & PN_TERM_RR) != 0;
+
+    Io io;
+    io.m = m; io.S0 = S0; io.L0 = L0; io.w0 = omega0;
+    io.y = y_final; io.t = t_final; io.steps = steps; io.status = status; io.dots = dots;
+
+    unsigned long long* counter = ctx->counters + (ctx->next.fetch_add(1) % kCounterSlots);
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e;
+    switch (block) {
+        case 64: e = launch_forward<64>(io, u, o.schedule, wps, ctx->cus, counter, s); break;
+        case 128: e = launch_forward<128>(io, u, o.schedule, wps, ctx->cus, counter, s); break;
+        case 512: e = launch_forward<512>(io, u, o.schedule, wps, ctx->cus, counter, s); break;
+        case 1024: e = launch_forward<1024>(io, u, o.schedule, wps, ctx->cus, counter, s); break;
+        default: e = launch_forward<256>(io, u, o.schedule, wps, ctx->cus, counter, s); break;
+    }
+    return e == hipSuccess ? PN_OK : PN_EHIP;
+}
+
+int pn_rhs(int64_t n, int64_t ld, const double* m, const double* y, double* dydt, const pn_opts* opt,
+           void* stream) {
+    if (n < 0 || ld < n) return PN_EINVAL;
+    if (n > 0 && (!m || !y || !dydt)) return PN_EINVAL;
+    const int terms = (opt && opt->terms > 0) ? opt->terms : PN_TERM_ALL;
+    const int lit = opt ? opt->theta_literal : 0;
+    if ((opt && opt->terms > PN_TERM_ALL) || (lit != 0 && lit != 1)) return PN_EINVAL;
+    if (n == 0) return PN_OK;
+    DevCtx* ctx = nullptr;
+    int rc = get_ctx(&ctx);
+    if (rc != PN_OK) return rc;
+    const int64_t grid = (n + 255) / 256;
+    hipLaunchKernelGGL(rhs_kernel, dim3((unsigned)grid), dim3(256), 0, (hipStream_t)stream, n, ld, m, y,
+                       dydt, terms, lit, term_consts(terms));
+    return hipGetLastError() == hipSuccess ? PN_OK : PN_EHIP;
+}
+
+int pn_observables(int64_t n, int64_t ld, const double* y, double* dots, void* stream) {
+    if (n < 0 || ld < n) return PN_EINVAL;
+    if (n > 0 && (!y || !dots)) return PN_EINVAL;
+    if (n == 0) return PN_OK;
+    DevCtx* ctx = nullptr;
+    int rc = get_ctx(&ctx);
+    if (rc != PN_OK) return rc;
+    const int64_t grid = (n + 255) / 256;
+    hipLaunchKernelGGL(observables_kernel, dim3((unsigned)grid), dim3(256), 0, (hipStream_t)stream, n, ld, y,
+                       dots);
+    return hipGetLastError() == hipSuccess ? PN_OK : PN_EHIP;
+}
+
+}  // extern "C"

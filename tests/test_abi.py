@@ -1,0 +1,75 @@
+"""The C interface without a GPU: the library loads, exports every entry
+point that include/pn.h declares, and rejects invalid arguments before it
+touches a device."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "pn.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(pn_[a-z_0-9]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_0908_3889_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.fail("libpn.so is not built (run __graft_entry__.build())")
+    return _lib.load()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _declared()
+    assert {"pn_integrate", "pn_rhs", "pn_observables", "pn_strerror"} <= set(names)
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_binding_covers_the_header():
+    from paper_0908_3889_amd import _lib
+    assert set(_lib.EXPORTS) == set(_declared())
+
+
+def test_strerror_and_version(lib):
+    for code in (0, -1, -2, -3, -4):
+        assert lib.pn_strerror(code).decode().startswith("PN_")
+    assert lib.pn_version().decode()
+
+
+def test_opts_struct_layout_matches_header():
+    from paper_0908_3889_amd._lib import PnOpts
+    # 3 doubles, one int64, six int32
+    assert C.sizeof(PnOpts) == 3 * 8 + 8 + 6 * 4
+
+
+def test_invalid_arguments_return_einval_without_a_device(lib):
+    from paper_0908_3889_amd._lib import PnOpts, PN_EINVAL, PN_OK
+    z = C.c_void_p(0)
+    fake = C.c_void_p(0x1000)       # never dereferenced: validation fails first
+    o = PnOpts()
+    call = lambda n, ld, tol=1e-8, wf=0.05, ptr=fake, opt=o: lib.pn_integrate(
+        n, ld, ptr, ptr, ptr, ptr, wf, tol, C.byref(opt), ptr, ptr, ptr, ptr, z, z)
+    assert call(-1, 0) == PN_EINVAL
+    assert call(10, 5) == PN_EINVAL
+    assert call(10, 10, ptr=z) == PN_EINVAL
+    assert call(10, 10, tol=0.0) == PN_EINVAL
+    assert call(10, 10, tol=float("nan")) == PN_EINVAL
+    assert call(10, 10, wf=-1.0) == PN_EINVAL
+    bad = PnOpts(); bad.block = 96
+    assert call(10, 10, opt=bad) == PN_EINVAL
+    bad = PnOpts(); bad.schedule = 7
+    assert call(10, 10, opt=bad) == PN_EINVAL
+    bad = PnOpts(); bad.h_fixed = -1.0
+    assert call(10, 10, opt=bad) == PN_EINVAL
+    bad = PnOpts(); bad.terms = 64
+    assert call(10, 10, opt=bad) == PN_EINVAL
+    assert call(0, 0) == PN_OK                       # empty batch: nothing to do
+    assert lib.pn_rhs(-1, 0, fake, fake, fake, None, z) == PN_EINVAL
+    assert lib.pn_observables(5, 4, fake, fake, z) == PN_EINVAL
+    assert lib.pn_observables(0, 0, fake, fake, z) == PN_OK

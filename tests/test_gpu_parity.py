@@ -1,0 +1,308 @@
+"""Parity of the gfx950 path (through the C interface) with the CPU oracle on
+the same seeded inputs.
+
+Tolerances: the right-hand side to 1e-14 relative; fixed-step integration
+to 1e-12 normwise relative (omega by |omega|, S_i by |S_i(0)|, L_hat by 1);
+adaptive integration to 1e-8 absolute on the three final unit-vector dot
+products, with the step counts equal.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from helpers import normwise_rel, run_gpu, run_oracle, state0
+from paper_0908_3889_amd import population as P
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_0908_3889_amd import _lib
+    _lib.load()   # fails loudly if the library is missing
+    yield
+
+
+def _api():
+    from paper_0908_3889_amd import api
+    return api
+
+
+def _random_states(n, seed):
+    rng = np.random.default_rng(seed)
+    q = rng.uniform(1, 10, n)
+    m = np.stack([q / (1 + q), 1 / (1 + q)])
+    u = rng.normal(size=(3, 3, n))
+    u /= np.linalg.norm(u, axis=1, keepdims=True)
+    chi = rng.uniform(0, 1, (2, n))
+    y = np.concatenate([rng.uniform(0.002, 0.1, (1, n)), chi[0] * m[0] ** 2 * u[0],
+                        chi[1] * m[1] ** 2 * u[1], u[2]])
+    return m, y
+
+
+# ---------------------------------------------------------------------------
+# right-hand side
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("terms", [63, 8, 1 | 8, 2 | 8, 4 | 8, 16, 32, 63 & ~8])
+@pytest.mark.parametrize("theta_literal", [0, 1])
+def test_rhs_parity(terms, theta_literal):
+    api = _api()
+    m, y = _random_states(1000, 1)
+    ref = oracle.rhs(m, y, terms=terms, theta_literal=theta_literal)
+    got = api.pn_rhs(torch.from_numpy(m).cuda(), torch.from_numpy(y).cuda(),
+                     api.make_opts(terms=terms, theta_literal=theta_literal)).cpu().numpy()
+    sc0 = np.maximum(np.abs(ref[0]), 1e-300)
+    assert (np.abs(got[0] - ref[0]) <= 1e-14 * sc0 + (ref[0] == 0)).all()
+    # the spin and L_hat derivatives are sums of cross products that can
+    # cancel: compare against the size of the summed terms of Eq. (4) x S_i
+    m1, m2 = m
+    M = m1 + m2
+    eta = m1 * m2 / M ** 2
+    v = M * y[0]
+    x = np.cbrt(v)
+    p = v / (2 * M)
+    S1, S2, L = y[1:4], y[4:7], y[7:10]
+    nS1, nS2 = np.linalg.norm(S1, axis=0), np.linalg.norm(S2, axis=0)
+    so = 1.0 if terms & 16 else 0.0
+    ss = 1.0 if terms & 32 else 0.0
+    sig = 1 / M ** 2
+    t1 = p * nS1 * (so * eta * (4 + 3 * m2 / m1) * x ** 2 + ss * sig * v * (nS2 + 3 * np.abs((L * S2).sum(0))))
+    t2 = p * nS2 * (so * eta * (4 + 3 * m1 / m2) * x ** 2 + ss * sig * v * (nS1 + 3 * np.abs((L * S1).sum(0))))
+    tl = x / (eta * M ** 2) * (t1 + t2)
+    for s, sc in ((slice(1, 4), t1), (slice(4, 7), t2), (slice(7, 10), tl)):
+        err = np.abs(got[s] - ref[s]).max(axis=0)
+        assert (err <= 1e-14 * sc + 1e-300).all(), (err / np.maximum(sc, 1e-300)).max()
+
+
+def test_rhs_parity_off_the_physical_region():
+    """Stage points of rejected or fixed steps can leave the physical region:
+    omega <= 0 or large, spins of any size, L_hat not unit.  The right-hand
+    side is the same real-valued function there."""
+    api = _api()
+    rng = np.random.default_rng(3)
+    n = 4000
+    q = rng.uniform(1, 10, n)
+    m = np.stack([q / (1 + q), 1 / (1 + q)])
+    y = np.concatenate([rng.uniform(-0.05, 0.5, (1, n)),
+                        rng.normal(size=(9, n)) * rng.uniform(0.01, 5, (1, n))])
+    y[0, :4] = [1e-300, -1e-300, 1e200, -1e200]
+    ref = oracle.rhs(m, y)
+    got = api.pn_rhs(torch.from_numpy(m).cuda(), torch.from_numpy(y).cuda()).cpu().numpy()
+    fin = np.isfinite(ref).all(axis=0)
+    assert (np.isfinite(got).all(axis=0) == fin).all()
+    rel = np.abs(got - ref)[:, fin] / np.maximum(np.abs(ref[:, fin]).max(axis=0), 1e-300)
+    assert rel.max() < 1e-12, rel.max()
+
+
+def test_observables_parity():
+    api = _api()
+    _, y = _random_states(777, 2)
+    y[1:4, :5] = 0.0                                  # zero spin: dot defined as 0
+    ref = oracle.observables(y)
+    got = api.pn_observables(torch.from_numpy(y).cuda()).cpu().numpy()
+    np.testing.assert_allclose(got, ref, rtol=0, atol=1e-15)
+
+
+# ---------------------------------------------------------------------------
+# fixed-step integration: 1e-12 normwise relative
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("workload,h", [("equal_mass_maxspin_1k", 40.0), ("adjoint_64k", 50.0),
+                                        ("q1to4_1M", 100.0), ("batching_4M", 100.0)])
+def test_fixed_step_parity(workload, h):
+    """1e-12 normwise relative, or 1e-15 per step for runs longer than 1000
+    steps (the batching workload takes up to ~35,000 fixed steps, over which
+    independent roundings accumulate past 1e-12)."""
+    pop = P.generate(workload, 777)          # several waves and a ragged tail
+    ro = run_oracle(pop, h_fixed=h)
+    rg = run_gpu(pop, h_fixed=h)
+    assert (rg["status"] == ro["status"]).all()
+    np.testing.assert_array_equal(rg["steps"][:2], ro["steps"][:2])
+    bound = np.maximum(1e-12, 1e-15 * ro["steps"][0])
+    err = normwise_rel(rg["y"], ro["y"], pop["S"])
+    assert (err < bound).all(), (err / bound).max()
+    assert (np.abs(rg["t"] / ro["t"] - 1) < bound).all()
+
+
+def test_fixed_step_t_end_parity():
+    pop = P.generate("q1to4_1M", 300)
+    ro = run_oracle(pop, h_fixed=100.0, t_end=5.0e4)
+    rg = run_gpu(pop, h_fixed=100.0, t_end=5.0e4)
+    assert (rg["status"] == 0).all() and (ro["status"] == 0).all()
+    assert normwise_rel(rg["y"], ro["y"], pop["S"]).max() < 1e-12
+    np.testing.assert_array_equal(rg["t"], ro["t"])
+
+
+# ---------------------------------------------------------------------------
+# adaptive integration: 1e-8 on the dot products, identical step counts
+# ---------------------------------------------------------------------------
+
+def _adaptive_check(pop, rg, ro, atol=1e-8):
+    assert (rg["status"] == ro["status"]).all()
+    ok = rg["status"] == 0
+    dd = np.abs(rg["dots"] - ro["dots"]).max(axis=0)
+    assert dd.max() < atol, (dd.max(), int(dd.argmax()))
+    same = (rg["steps"][0] == ro["steps"][0]) & (rg["steps"][1] == ro["steps"][1])
+    assert same.mean() == 1.0, f"{(~same).sum()} inspirals took other step counts"
+    assert (rg["y"][0][ok] == pop["omega_f"]).all()
+    assert np.abs(rg["t"] / ro["t"] - 1)[ok].max() < 1e-9
+
+
+def test_adaptive_parity_equal_mass_1k_full():
+    pop = P.generate("equal_mass_maxspin_1k")       # 1,024 inspirals, tol 1e-10
+    _adaptive_check(pop, run_gpu(pop), run_oracle(pop))
+
+
+@pytest.mark.parametrize("workload,n", [("q1to4_1M", 4099), ("batching_4M", 2049),
+                                        ("adjoint_64k", 1000), ("paper_equal_mass", 640)])
+def test_adaptive_parity_prefix(workload, n):
+    pop = P.generate(workload, n)
+    _adaptive_check(pop, run_gpu(pop), run_oracle(pop))
+
+
+def test_adaptive_t_end_parity():
+    pop = P.generate("adjoint_64k", 500)
+    ro = run_oracle(pop, t_end=12000.0)
+    rg = run_gpu(pop, t_end=12000.0)
+    assert (rg["status"] == 0).all()
+    np.testing.assert_array_equal(rg["steps"][:2], ro["steps"][:2])
+    assert normwise_rel(rg["y"], ro["y"], pop["S"]).max() < 1e-9
+
+
+@pytest.mark.parametrize("terms", [8, 1 | 8, 63 & ~32, 63 & ~4])
+def test_adaptive_parity_term_subsets(terms):
+    pop = P.generate("adjoint_64k", 300)
+    _adaptive_check(pop, run_gpu(pop, terms=terms), run_oracle(pop, terms=terms))
+
+
+# ---------------------------------------------------------------------------
+# schedules and launch shapes give identical results
+# ---------------------------------------------------------------------------
+
+def test_schedules_and_launch_shapes_agree_bitwise():
+    pop = P.generate("batching_4M", 3001)
+    base = run_gpu(pop)
+    for kw in (dict(schedule="static"), dict(block=64), dict(block=128, waves_per_simd=1),
+               dict(waves_per_simd=4), dict(refill_min=8), dict(block=64, waves_per_simd=1)):
+        other = run_gpu(pop, **kw)
+        for k in ("y", "t", "steps", "status", "dots"):
+            np.testing.assert_array_equal(other[k], base[k], err_msg=f"{kw} {k}")
+
+
+# ---------------------------------------------------------------------------
+# status codes and edge sizes
+# ---------------------------------------------------------------------------
+
+def test_status_codes_match_oracle():
+    pop = P.generate("q1to4_1M", 70)
+    pop["omega0"] = pop["omega0"].copy(); pop["m"] = pop["m"].copy(); pop["S"] = pop["S"].copy()
+    pop["omega0"][0] = 0.06                 # done at start
+    pop["omega0"][1] = 0.05                 # omega0 == omega_f: done at start
+    pop["m"][1, 2] = 0.0                    # bad mass
+    pop["S"][4, 3] = np.nan                 # non-finite input
+    pop["omega0"][4] = -0.01                # bad omega0
+    pop["m"][0, 5] = np.inf
+    ro, rg = run_oracle(pop), run_gpu(pop)
+    np.testing.assert_array_equal(rg["status"], ro["status"])
+    assert list(rg["status"][:6]) == [1, 1, -4, -4, -4, -4]
+    np.testing.assert_array_equal(rg["steps"][:, :6], 0)
+    np.testing.assert_array_equal(rg["y"][:, :2], state0(pop)[:, :2])
+    _adaptive_check(P.subset(pop, np.arange(6, 70)), {k: v[..., 6:] for k, v in rg.items()},
+                    {k: v[..., 6:] for k, v in ro.items()})
+
+
+def test_max_steps_and_underflow_and_nonfinite():
+    """MAX_STEPS stops at a step count, not at omega_f, so the states are
+    compared at slightly different times: while err << 1 the embedded error
+    estimate is a difference of nearly equal terms and carries ~1e-7
+    relative rounding noise on both sides, so the step sizes agree only to
+    ~1e-8 relative.  (At omega_f that time shift drops out.)"""
+    pop = P.generate("q1to4_1M", 130)
+    for ms in (1, 3, 7, 40):
+        ro, rg = run_oracle(pop, max_steps=ms), run_gpu(pop, max_steps=ms)
+        assert (rg["status"] == -1).all() and (ro["status"] == -1).all()
+        np.testing.assert_array_equal(rg["steps"], ro["steps"])
+        assert np.abs(rg["t"] / ro["t"] - 1).max() < 1e-7
+        assert normwise_rel(rg["y"], ro["y"], pop["S"]).max() < 1e-7
+    p2 = dict(pop); p2["tol"] = 1e-300
+    ro, rg = run_oracle(p2), run_gpu(p2)
+    assert (rg["status"] == -2).all() and (ro["status"] == -2).all()
+    np.testing.assert_array_equal(rg["steps"][:2], ro["steps"][:2])
+    p3 = dict(pop); p3["omega0"] = np.full(130, 1e80)
+    ro, rg = run_oracle(p3, t_end=10.0), run_gpu(p3, t_end=10.0)
+    assert (rg["status"] == -3).all() and (ro["status"] == -3).all()
+
+
+@pytest.mark.parametrize("n", [0, 1, 63, 65, 257])
+def test_edge_sizes(n):
+    pop = P.generate("adjoint_64k", n)
+    rg = run_gpu(pop)
+    if n == 0:
+        assert rg["y"].shape == (10, 0)
+        return
+    _adaptive_check(pop, rg, run_oracle(pop))
+
+
+def test_leading_dimension_larger_than_n():
+    api = _api()
+    pop = P.generate("adjoint_64k", 100)
+    ld = 128
+    dev = {}
+    for k, c in (("m", 2), ("S", 6), ("L", 3)):
+        buf = torch.full((c, ld), float("nan"), dtype=torch.float64, device="cuda")
+        buf[:, :100] = torch.from_numpy(pop[k])
+        dev[k] = buf[:, :100]
+    w0 = torch.from_numpy(pop["omega0"]).cuda()
+    bufs = {k: torch.full((c, ld), -7, dtype=dt, device="cuda")
+            for k, c, dt in (("y", 10, torch.float64), ("steps", 3, torch.int32),
+                             ("dots", 3, torch.float64))}
+    out = {k: b[:, :100] for k, b in bufs.items()}
+    out["t"] = torch.empty(100, dtype=torch.float64, device="cuda")
+    out["status"] = torch.empty(100, dtype=torch.int32, device="cuda")
+    api.pn_integrate(dev["m"], dev["S"], dev["L"], w0, pop["omega_f"], pop["tol"], out=out)
+    torch.cuda.synchronize()
+    ro = run_oracle(pop)
+    rg = {k: v.cpu().numpy() for k, v in out.items()}
+    _adaptive_check(pop, rg, ro)
+    for b in bufs.values():                      # padding columns untouched
+        assert (b[:, 100:] == -7).all()
+
+
+def test_invalid_arguments_rejected():
+    api = _api()
+    from paper_0908_3889_amd._lib import PnError
+    pop = P.generate("adjoint_64k", 10)
+    d = api.to_device(pop)
+    with pytest.raises(PnError):
+        api.pn_integrate(d["m"], d["S"], d["L"], d["omega0"], pop["omega_f"], -1.0)
+    with pytest.raises(PnError):
+        api.pn_integrate(d["m"], d["S"], d["L"], d["omega0"], 0.0, 1e-8)
+    with pytest.raises(PnError):
+        api.pn_integrate(d["m"], d["S"], d["L"], d["omega0"], 0.05, 1e-8, api.make_opts(block=96))
+
+
+# ---------------------------------------------------------------------------
+# full-size runs: every status OK, sampled inspirals against the oracle
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("workload,sample", [("q1to4_1M", 1500), ("batching_4M", 800)])
+def test_full_size_sampled_parity(workload, sample):
+    pop = P.generate(workload)
+    rg = run_gpu(pop)
+    assert (rg["status"] == 0).all()
+    assert (rg["y"][0] == pop["omega_f"]).all()
+    rng = np.random.default_rng(7)
+    idx = np.sort(rng.choice(pop["n"], sample, replace=False))
+    idx[-1] = pop["n"] - 1
+    sub = P.subset(pop, idx)
+    ro = run_oracle(sub)
+    _adaptive_check(sub, {k: v[..., idx] for k, v in rg.items()}, ro)
+    # properties that hold everywhere: unit L_hat, spin norms, omega exactly omega_f
+    n1 = np.linalg.norm(rg["y"][1:4], axis=0) / np.maximum(np.linalg.norm(pop["S"][:3], axis=0), 1e-300)
+    assert np.abs(np.linalg.norm(rg["y"][7:], axis=0) - 1).max() < 1e-5
+    assert np.abs(n1 - 1)[np.linalg.norm(pop["S"][:3], axis=0) > 1e-3].max() < 1e-3
