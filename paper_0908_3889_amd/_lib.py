@@ -8,7 +8,8 @@ import ctypes as C
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libpn.so")
+# PN_LIB may name another build of the same library (for A/B timing)
+LIB_PATH = os.environ.get("PN_LIB") or os.path.join(HERE, "libpn.so")
 
 # return codes
 PN_OK, PN_EINVAL, PN_ENODEV, PN_EHIP, PN_ENOMEM = 0, -1, -2, -3, -4

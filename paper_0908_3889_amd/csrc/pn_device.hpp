@@ -112,23 +112,40 @@ __device__ __forceinline__ double pow_m_tenth(double z) {
 // Per-inspiral coefficient row: everything in Eqs. (1)-(4) that depends only
 // on (m1, m2) and the term switches.  Built once per inspiral.
 // ---------------------------------------------------------------------------
+enum RowIdx {
+    R_M = 0,   // m1 + m2
+    R_C2,      // -(743 + 924 eta)/336                                (M w)^{2/3}
+    R_SO1,     // (113 m1^2/M^2 + 75 eta)/(12 m1^2)  [times L.S1]     (M w)^{1}
+    R_SO2,     // (113 m2^2/M^2 + 75 eta)/(12 m2^2)  [times L.S2]
+    R_C4,      // 34103/18144 + 13661/2016 eta + 59/18 eta^2          (M w)^{4/3}
+    R_SS1,     // 247 eta / (48 m1^2 m2^2)            [times S1.S2]
+    R_SS2,     // 721 eta / (48 m1^2 m2^2)            [times L.S1 L.S2]
+    R_C5,      // -(4159 + 15876 eta) pi / 672                        (M w)^{5/3}
+    R_C6,      // 3PN constant part, -(856/105) ln 16 included        (M w)^{2}
+    R_C7,      // (-4415/4032 + 358675/6048 eta + 91495/1512 eta^2) pi (M w)^{7/3}
+    R_K,       // (96/5) eta / M^2: d omega/dt = K (M w)^2 x^5 {...}
+    R_HINVM,   // 1/(2M)
+    R_G1,      // eta (4 + 3 m2/m1)
+    R_G2,      // eta (4 + 3 m1/m2)
+    R_SIG,     // 1/M^2
+    R_LAM,     // 1/(eta M^2)
+    NROW
+};
+
+// the row held in registers (test kernels)
 struct Row {
-    double M;      // m1 + m2
-    double c2;     // -(743 + 924 eta)/336                                (M w)^{2/3}
-    double so1;    // (113 m1^2/M^2 + 75 eta)/(12 m1^2)  [times L.S1]     (M w)^{1}
-    double so2;    // (113 m2^2/M^2 + 75 eta)/(12 m2^2)  [times L.S2]
-    double c4;     // 34103/18144 + 13661/2016 eta + 59/18 eta^2          (M w)^{4/3}
-    double ss1;    // 247 eta / (48 m1^2 m2^2)            [times S1.S2]
-    double ss2;    // 721 eta / (48 m1^2 m2^2)            [times L.S1 L.S2]
-    double c5;     // -(4159 + 15876 eta) pi / 672                        (M w)^{5/3}
-    double c6;     // 3PN constant part, -(856/105) ln 16 included        (M w)^{2}
-    double c7;     // (-4415/4032 + 358675/6048 eta + 91495/1512 eta^2) pi (M w)^{7/3}
-    double K;      // (96/5) eta / M^2: d omega/dt = K (M w)^2 x^5 {...}
-    double hinvM;  // 1/(2M)
-    double g1;     // eta (4 + 3 m2/m1)
-    double g2;     // eta (4 + 3 m1/m2)
-    double sig;    // 1/M^2
-    double lam;    // 1/(eta M^2)
+    double v[NROW];
+    __device__ __forceinline__ double operator[](int i) const { return v[i]; }
+    __device__ __forceinline__ void set(int i, double x) { v[i] = x; }
+};
+
+// the row held in LDS, one column per lane: entry i of this lane at p[i * 64].
+// Reads are volatile so that every right-hand-side evaluation reads the row
+// again instead of the compiler keeping 16 doubles in registers.
+struct RowLds {
+    volatile double* p;
+    __device__ __forceinline__ double operator[](int i) const { return p[i * 64]; }
+    __device__ __forceinline__ void set(int i, double x) const { p[i * 64] = x; }
 };
 
 // Launch-uniform switches folded into numbers: 4 pi and -1712/105 when the
@@ -142,39 +159,38 @@ struct TermConsts {
 #define PN_GAMMA_E 0.57721566490153286061
 #define PN_LN16 2.77258872223978123767
 
-__device__ __forceinline__ Row make_row(double m1, double m2, int terms, int theta_literal) {
-    Row r;
+template <class RowT>
+__device__ __forceinline__ void make_row(RowT& r, double m1, double m2, int terms, int theta_literal) {
     const double M = m1 + m2;
     const double iM = 1.0 / M;
     const double eta = m1 * m2 * iM * iM;
     const double pn = (terms & PN_TERM_PN) ? 1.0 : 0.0;
     const double fso = (terms & PN_TERM_SO_WDOT) ? 1.0 : 0.0;
     const double fss = (terms & PN_TERM_SS_WDOT) ? 1.0 : 0.0;
-    r.M = M;
-    r.c2 = pn * (-(743.0 + 924.0 * eta) / 336.0);
-    r.so1 = fso * (113.0 * m1 * m1 * iM * iM + 75.0 * eta) / (12.0 * m1 * m1);
-    r.so2 = fso * (113.0 * m2 * m2 * iM * iM + 75.0 * eta) / (12.0 * m2 * m2);
-    r.c4 = pn * (34103.0 / 18144.0 + (13661.0 / 2016.0) * eta + (59.0 / 18.0) * eta * eta);
+    r.set(R_M, M);
+    r.set(R_C2, pn * (-(743.0 + 924.0 * eta) / 336.0));
+    r.set(R_SO1, fso * (113.0 * m1 * m1 * iM * iM + 75.0 * eta) / (12.0 * m1 * m1));
+    r.set(R_SO2, fso * (113.0 * m2 * m2 * iM * iM + 75.0 * eta) / (12.0 * m2 * m2));
+    r.set(R_C4, pn * (34103.0 / 18144.0 + (13661.0 / 2016.0) * eta + (59.0 / 18.0) * eta * eta));
     const double ssd = eta / (48.0 * m1 * m1 * m2 * m2);
-    r.ss1 = fss * 247.0 * ssd;
-    r.ss2 = fss * 721.0 * ssd;
-    r.c5 = pn * (-(4159.0 + 15876.0 * eta) * PN_PI / 672.0);
+    r.set(R_SS1, fss * 247.0 * ssd);
+    r.set(R_SS2, fss * 721.0 * ssd);
+    r.set(R_C5, pn * (-(4159.0 + 15876.0 * eta) * PN_PI / 672.0));
     // 3PN: theta_hat = 1039/4620 multiplies eta once (the expansion of
     // Eq. (1)'s source), or, with theta_literal, eta^2 as printed.
     const double theta_term = (88.0 / 3.0) * (1039.0 / 4620.0) * (theta_literal ? eta : 1.0);
-    r.c6 = pn * ((16447322263.0 / 139708800.0) - (1712.0 / 105.0) * PN_GAMMA_E
-                 + (16.0 / 3.0) * PN_PI * PN_PI
-                 + (-273811877.0 / 1088640.0 + (451.0 / 48.0) * PN_PI * PN_PI - theta_term) * eta
-                 + (541.0 / 896.0) * eta * eta - (5605.0 / 2592.0) * eta * eta * eta
-                 - (856.0 / 105.0) * PN_LN16);
-    r.c7 = pn * ((-4415.0 / 4032.0 + (358675.0 / 6048.0) * eta + (91495.0 / 1512.0) * eta * eta) * PN_PI);
-    r.K = (terms & PN_TERM_RR) ? (96.0 / 5.0) * eta * iM * iM : 0.0;
-    r.hinvM = 0.5 * iM;
-    r.g1 = (terms & PN_TERM_SO_PREC) ? eta * (4.0 + 3.0 * m2 / m1) : 0.0;
-    r.g2 = (terms & PN_TERM_SO_PREC) ? eta * (4.0 + 3.0 * m1 / m2) : 0.0;
-    r.sig = (terms & PN_TERM_SS_PREC) ? iM * iM : 0.0;
-    r.lam = 1.0 / (eta * M * M);
-    return r;
+    r.set(R_C6, pn * ((16447322263.0 / 139708800.0) - (1712.0 / 105.0) * PN_GAMMA_E
+                      + (16.0 / 3.0) * PN_PI * PN_PI
+                      + (-273811877.0 / 1088640.0 + (451.0 / 48.0) * PN_PI * PN_PI - theta_term) * eta
+                      + (541.0 / 896.0) * eta * eta - (5605.0 / 2592.0) * eta * eta * eta
+                      - (856.0 / 105.0) * PN_LN16));
+    r.set(R_C7, pn * ((-4415.0 / 4032.0 + (358675.0 / 6048.0) * eta + (91495.0 / 1512.0) * eta * eta) * PN_PI));
+    r.set(R_K, (terms & PN_TERM_RR) ? (96.0 / 5.0) * eta * iM * iM : 0.0);
+    r.set(R_HINVM, 0.5 * iM);
+    r.set(R_G1, (terms & PN_TERM_SO_PREC) ? eta * (4.0 + 3.0 * m2 / m1) : 0.0);
+    r.set(R_G2, (terms & PN_TERM_SO_PREC) ? eta * (4.0 + 3.0 * m1 / m2) : 0.0);
+    r.set(R_SIG, (terms & PN_TERM_SS_PREC) ? iM * iM : 0.0);
+    r.set(R_LAM, 1.0 / (eta * M * M));
 }
 
 // dy/dt of Eqs. (1)-(4) at y = (w, S1, S2, L).  Returns d omega/dt in d[0].
@@ -190,9 +206,10 @@ __device__ __forceinline__ Row make_row(double m1, double m2, int terms, int the
 // Off the physical region (stage points of rejected or fixed steps) omega may
 // be negative; x is then the real cube root and the log term uses
 // ln(16 x^2) = ln 16 + (2/3) ln|v|, which is what Eq. (1) gives for any real x.
-__device__ __forceinline__ void rhs(const Row& r, const TermConsts& tc, const double* __restrict__ y,
+template <class RowT>
+__device__ __forceinline__ void rhs(const RowT& r, const TermConsts& tc, const double* __restrict__ y,
                                     double* __restrict__ d) {
-    const double v = r.M * y[0];
+    const double v = r[R_M] * y[0];
     const double x = cbrt_real(v);
     const double lnx = log_pos(__builtin_fabs(v)) * (1.0 / 3.0);
     const double x2 = x * x;
@@ -203,22 +220,22 @@ __device__ __forceinline__ void rhs(const Row& r, const TermConsts& tc, const do
     const double LS2 = __builtin_fma(L0, b0, __builtin_fma(L1, b1, L2 * b2));
     const double S12 = __builtin_fma(a0, b0, __builtin_fma(a1, b1, a2 * b2));
 
-    const double c3p = __builtin_fma(-r.so2, LS2, __builtin_fma(-r.so1, LS1, tc.c3));
-    const double c4p = __builtin_fma(r.ss2 * LS1, LS2, __builtin_fma(-r.ss1, S12, r.c4));
-    const double c6p = __builtin_fma(tc.c6log, lnx, r.c6);
-    double B = __builtin_fma(x, r.c7, c6p);
-    B = __builtin_fma(x, B, r.c5);
+    const double c3p = __builtin_fma(-r[R_SO2], LS2, __builtin_fma(-r[R_SO1], LS1, tc.c3));
+    const double c4p = __builtin_fma(r[R_SS2] * LS1, LS2, __builtin_fma(-r[R_SS1], S12, r[R_C4]));
+    const double c6p = __builtin_fma(tc.c6log, lnx, r[R_C6]);
+    double B = __builtin_fma(x, r[R_C7], c6p);
+    B = __builtin_fma(x, B, r[R_C5]);
     B = __builtin_fma(x, B, c4p);
     B = __builtin_fma(x, B, c3p);
-    B = __builtin_fma(x, B, r.c2);
+    B = __builtin_fma(x, B, r[R_C2]);
     B = __builtin_fma(x2, B, 1.0);
     const double x5 = x2 * x2 * x;
-    d[0] = (r.K * (v * v)) * x5 * B;
+    d[0] = (r[R_K] * (v * v)) * x5 * B;
 
-    const double p = v * r.hinvM;
-    const double sv = r.sig * v;
-    const double al1 = p * __builtin_fma(r.g1, x2, -3.0 * sv * LS2);
-    const double al2 = p * __builtin_fma(r.g2, x2, -3.0 * sv * LS1);
+    const double p = v * r[R_HINVM];
+    const double sv = r[R_SIG] * v;
+    const double al1 = p * __builtin_fma(r[R_G1], x2, -3.0 * sv * LS2);
+    const double al2 = p * __builtin_fma(r[R_G2], x2, -3.0 * sv * LS1);
     const double be = p * sv;
     // L x S1, L x S2, S1 x S2
     const double u0 = __builtin_fma(L1, a2, -L2 * a1), u1 = __builtin_fma(L2, a0, -L0 * a2),
@@ -233,7 +250,7 @@ __device__ __forceinline__ void rhs(const Row& r, const TermConsts& tc, const do
     d[4] = __builtin_fma(al2, w0, be * c0);
     d[5] = __builtin_fma(al2, w1, be * c1);
     d[6] = __builtin_fma(al2, w2, be * cc2);
-    const double q = -r.lam * x;
+    const double q = -r[R_LAM] * x;
     d[7] = q * (d[1] + d[4]);
     d[8] = q * (d[2] + d[5]);
     d[9] = q * (d[3] + d[6]);

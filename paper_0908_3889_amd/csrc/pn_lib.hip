@@ -18,6 +18,11 @@
 #include "pn.h"
 #include "pn_device.hpp"
 
+// Occupancy the integration kernels are compiled for (waves per SIMD).
+#ifndef PN_WAVES_PER_EU
+#define PN_WAVES_PER_EU 2
+#endif
+
 namespace pn {
 
 // ---------------------------------------------------------------------------
@@ -68,7 +73,7 @@ struct Lane {
     double k1[10];
     double dt1;       // dt/d(variable) of k1: 1 in time mode, 1/omega-dot in omega mode
     double t, h;
-    Row row;
+    RowLds row;       // this lane's coefficient column in LDS
     int64_t idx;
     int acc, rej, nrhs;
     bool omega_mode, last_rej;
@@ -129,7 +134,7 @@ __device__ int load_lane(const Io& io, const Uni& u, Lane& L, int64_t idx) {
     for (int c = 0; c < 10; ++c) bad = bad || !finite(L.y[c]);
     if (bad) { write_out(io, u, L, PN_ST_BAD_INPUT); return PN_ST_BAD_INPUT; }
     if (!u.tend && !(L.y[0] < u.omega_f)) { write_out(io, u, L, PN_ST_DONE_AT_START); return PN_ST_DONE_AT_START; }
-    L.row = make_row(m1, m2, u.terms, u.theta_literal);
+    make_row(L.row, m1, m2, u.terms, u.theta_literal);
     rhs(L.row, u.tc, L.y, L.k1);
     L.dt1 = 1.0;
     L.nrhs = 1;
@@ -155,11 +160,12 @@ __device__ __forceinline__ int step_lane(const Uni& u, Lane& L, bool any_w) {
         if (htry >= remain) { htry = remain; last = true; }
     }
 
-    const Row& R = L.row;
+    const RowLds R = L.row;
     const double* y = L.y;
     const double* k1 = L.k1;
     double Y[10], k2[10], k3[10], k4[10], k5[10], k6[10];
-    double dt2, dt3, dt4, dt5, dt6, dt7;
+    double dtj, dt7;
+    double dts = B1 * L.dt1;     // sum_j b_j dt_j, used in omega mode only
 
     const double h = htry;
     {
@@ -167,14 +173,14 @@ __device__ __forceinline__ int step_lane(const Uni& u, Lane& L, bool any_w) {
 #pragma unroll
         for (int c = 0; c < 10; ++c) Y[c] = __builtin_fma(c1, k1[c], y[c]);
         rhs(R, u.tc, Y, k2);
-        if (any_w) to_omega_variable(k2, dt2, L.omega_mode); else dt2 = 1.0;
+        if (any_w) to_omega_variable(k2, dtj, L.omega_mode);
     }
     {
         const double c1 = h * A31, c2 = h * A32;
 #pragma unroll
         for (int c = 0; c < 10; ++c) Y[c] = __builtin_fma(c2, k2[c], __builtin_fma(c1, k1[c], y[c]));
         rhs(R, u.tc, Y, k3);
-        if (any_w) to_omega_variable(k3, dt3, L.omega_mode); else dt3 = 1.0;
+        if (any_w) { to_omega_variable(k3, dtj, L.omega_mode); dts = __builtin_fma(B3, dtj, dts); }
     }
     {
         const double c1 = h * A41, c2 = h * A42, c3 = h * A43;
@@ -182,7 +188,7 @@ __device__ __forceinline__ int step_lane(const Uni& u, Lane& L, bool any_w) {
         for (int c = 0; c < 10; ++c)
             Y[c] = __builtin_fma(c3, k3[c], __builtin_fma(c2, k2[c], __builtin_fma(c1, k1[c], y[c])));
         rhs(R, u.tc, Y, k4);
-        if (any_w) to_omega_variable(k4, dt4, L.omega_mode); else dt4 = 1.0;
+        if (any_w) { to_omega_variable(k4, dtj, L.omega_mode); dts = __builtin_fma(B4, dtj, dts); }
     }
     {
         const double c1 = h * A51, c2 = h * A52, c3 = h * A53, c4 = h * A54;
@@ -191,7 +197,7 @@ __device__ __forceinline__ int step_lane(const Uni& u, Lane& L, bool any_w) {
             Y[c] = __builtin_fma(c4, k4[c], __builtin_fma(c3, k3[c],
                    __builtin_fma(c2, k2[c], __builtin_fma(c1, k1[c], y[c]))));
         rhs(R, u.tc, Y, k5);
-        if (any_w) to_omega_variable(k5, dt5, L.omega_mode); else dt5 = 1.0;
+        if (any_w) { to_omega_variable(k5, dtj, L.omega_mode); dts = __builtin_fma(B5, dtj, dts); }
     }
     {
         const double c1 = h * A61, c2 = h * A62, c3 = h * A63, c4 = h * A64, c5 = h * A65;
@@ -200,7 +206,7 @@ __device__ __forceinline__ int step_lane(const Uni& u, Lane& L, bool any_w) {
             Y[c] = __builtin_fma(c5, k5[c], __builtin_fma(c4, k4[c], __builtin_fma(c3, k3[c],
                    __builtin_fma(c2, k2[c], __builtin_fma(c1, k1[c], y[c])))));
         rhs(R, u.tc, Y, k6);
-        if (any_w) to_omega_variable(k6, dt6, L.omega_mode); else dt6 = 1.0;
+        if (any_w) { to_omega_variable(k6, dtj, L.omega_mode); dts = __builtin_fma(B6, dtj, dts); }
     }
     // stage 7 point = 5th-order solution; the error sum over k1, k3..k6 is
     // formed now so that those vectors die before the last RHS
@@ -217,7 +223,8 @@ __device__ __forceinline__ int step_lane(const Uni& u, Lane& L, bool any_w) {
     }
     double k7[10];
     rhs(R, u.tc, Y, k7);
-    if (any_w) to_omega_variable(k7, dt7, L.omega_mode); else dt7 = 1.0;
+    dt7 = 1.0;
+    if (any_w) to_omega_variable(k7, dt7, L.omega_mode);
     L.nrhs += 6;
 
     // error norm: z = err^2 = mean_c (e_c / (tol + tol max(|y_c|, |y5_c|)))^2
@@ -253,7 +260,6 @@ __device__ __forceinline__ int step_lane(const Uni& u, Lane& L, bool any_w) {
             return 0;
         }
         if (L.omega_mode) {
-            const double dts = B1 * L.dt1 + B3 * dt3 + B4 * dt4 + B5 * dt5 + B6 * dt6;
             L.t = __builtin_fma(h, dts, L.t);
         } else {
             L.t += h;
@@ -275,7 +281,6 @@ __device__ __forceinline__ int step_lane(const Uni& u, Lane& L, bool any_w) {
             L.h = h * fac;
             L.last_rej = false;
         }
-        (void)dt2;
         return 0;
     }
     // rejected
@@ -296,9 +301,12 @@ __device__ __forceinline__ uint64_t wave_ballot(bool p) { return __ballot(p); }
 // Persistent kernel: each wave loops, handing new inspirals to idle lanes
 // from a global counter, until the counter passes n and its lanes are done.
 template <int BLOCK>
-__global__ __launch_bounds__(BLOCK) void integrate_persistent(Io io, Uni u, unsigned long long* counter) {
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(PN_WAVES_PER_EU)))
+void integrate_persistent(Io io, Uni u, unsigned long long* counter) {
+    __shared__ double s_rows[BLOCK / 64][NROW][64];
     const int lane = lane_id();
     Lane L;
+    L.row.p = &s_rows[threadIdx.x / 64][0][lane];
     L.idx = -1;
     bool active = false;
     bool exhausted = false;     // wave-uniform
@@ -349,9 +357,12 @@ __global__ __launch_bounds__(BLOCK) void integrate_persistent(Io io, Uni u, unsi
 
 // One lane per inspiral, no refill: a wave runs until its longest inspiral ends.
 template <int BLOCK>
-__global__ __launch_bounds__(BLOCK) void integrate_static(Io io, Uni u) {
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(PN_WAVES_PER_EU)))
+void integrate_static(Io io, Uni u) {
+    __shared__ double s_rows[BLOCK / 64][NROW][64];
     const int64_t idx = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
     Lane L;
+    L.row.p = &s_rows[threadIdx.x / 64][0][lane_id()];
     bool active = false;
     if (idx < u.n) active = load_lane(io, u, L, idx) == 0;
     for (;;) {
@@ -373,7 +384,8 @@ __global__ void rhs_kernel(int64_t n, int64_t ld, const double* __restrict__ m, 
                            double* __restrict__ d, int terms, int theta_literal, TermConsts tc) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const Row r = make_row(m[i], m[ld + i], terms, theta_literal);
+    Row r;
+    make_row(r, m[i], m[ld + i], terms, theta_literal);
     double yy[10], dd[10];
 #pragma unroll
     for (int c = 0; c < 10; ++c) yy[c] = y[c * ld + i];
