@@ -118,16 +118,14 @@ enum RowIdx {
     R_SO1,     // (113 m1^2/M^2 + 75 eta)/(12 m1^2)  [times L.S1]     (M w)^{1}
     R_SO2,     // (113 m2^2/M^2 + 75 eta)/(12 m2^2)  [times L.S2]
     R_C4,      // 34103/18144 + 13661/2016 eta + 59/18 eta^2          (M w)^{4/3}
-    R_SS1,     // 247 eta / (48 m1^2 m2^2)            [times S1.S2]
-    R_SS2,     // 721 eta / (48 m1^2 m2^2)            [times L.S1 L.S2]
+    R_SSD,     // eta / (48 m1^2 m2^2) [times (247 S1.S2 - 721 L.S1 L.S2)]
     R_C5,      // -(4159 + 15876 eta) pi / 672                        (M w)^{5/3}
     R_C6,      // 3PN constant part, -(856/105) ln 16 included        (M w)^{2}
     R_C7,      // (-4415/4032 + 358675/6048 eta + 91495/1512 eta^2) pi (M w)^{7/3}
-    R_K,       // (96/5) eta / M^2: d omega/dt = K (M w)^2 x^5 {...}
-    R_HINVM,   // 1/(2M)
+    R_K,       // (96/5) eta: d omega/dt = K omega^2 x^5 {...}
     R_G1,      // eta (4 + 3 m2/m1)
     R_G2,      // eta (4 + 3 m1/m2)
-    R_SIG,     // 1/M^2
+    R_SIGM,    // 1/M: (1/M^2)(M w) = w/M in the spin-spin part of Eq. (4)
     R_LAM,     // 1/(eta M^2)
     NROW
 };
@@ -148,11 +146,11 @@ struct RowLds {
     __device__ __forceinline__ void set(int i, double x) const { p[i * 64] = x; }
 };
 
-// Launch-uniform switches folded into numbers: 4 pi and -1712/105 when the
+// Launch-uniform switches folded into numbers: 4 pi and -1712/315 when the
 // non-spinning PN terms are on, else 0.
 struct TermConsts {
     double c3;     // 4 pi
-    double c6log;  // coefficient of ln x, x = (M w)^{1/3}: -(856/105) * 2
+    double c6lnv;  // coefficient of ln|M w| in the 3PN bracket: -(856/105)(2/3) = -1712/315
 };
 
 #define PN_PI 3.14159265358979323846
@@ -172,9 +170,7 @@ __device__ __forceinline__ void make_row(RowT& r, double m1, double m2, int term
     r.set(R_SO1, fso * (113.0 * m1 * m1 * iM * iM + 75.0 * eta) / (12.0 * m1 * m1));
     r.set(R_SO2, fso * (113.0 * m2 * m2 * iM * iM + 75.0 * eta) / (12.0 * m2 * m2));
     r.set(R_C4, pn * (34103.0 / 18144.0 + (13661.0 / 2016.0) * eta + (59.0 / 18.0) * eta * eta));
-    const double ssd = eta / (48.0 * m1 * m1 * m2 * m2);
-    r.set(R_SS1, fss * 247.0 * ssd);
-    r.set(R_SS2, fss * 721.0 * ssd);
+    r.set(R_SSD, fss * eta / (48.0 * m1 * m1 * m2 * m2));
     r.set(R_C5, pn * (-(4159.0 + 15876.0 * eta) * PN_PI / 672.0));
     // 3PN: theta_hat = 1039/4620 multiplies eta once (the expansion of
     // Eq. (1)'s source), or, with theta_literal, eta^2 as printed.
@@ -185,33 +181,69 @@ __device__ __forceinline__ void make_row(RowT& r, double m1, double m2, int term
                       + (541.0 / 896.0) * eta * eta - (5605.0 / 2592.0) * eta * eta * eta
                       - (856.0 / 105.0) * PN_LN16));
     r.set(R_C7, pn * ((-4415.0 / 4032.0 + (358675.0 / 6048.0) * eta + (91495.0 / 1512.0) * eta * eta) * PN_PI));
-    r.set(R_K, (terms & PN_TERM_RR) ? (96.0 / 5.0) * eta * iM * iM : 0.0);
-    r.set(R_HINVM, 0.5 * iM);
+    r.set(R_K, (terms & PN_TERM_RR) ? (96.0 / 5.0) * eta : 0.0);
     r.set(R_G1, (terms & PN_TERM_SO_PREC) ? eta * (4.0 + 3.0 * m2 / m1) : 0.0);
     r.set(R_G2, (terms & PN_TERM_SO_PREC) ? eta * (4.0 + 3.0 * m1 / m2) : 0.0);
-    r.set(R_SIG, (terms & PN_TERM_SS_PREC) ? iM * iM : 0.0);
+    r.set(R_SIGM, (terms & PN_TERM_SS_PREC) ? iM : 0.0);
     r.set(R_LAM, 1.0 / (eta * M * M));
 }
+
+// ln(1+u) for |u| <= 1/8: 2 atanh(s), s = u/(2+u), |s| <= 0.0589, by the
+// series 2 (s + s^3/3 + ... + s^11/11) (relative remainder < 2e-16).
+__device__ __forceinline__ double log1p_small(double u) {
+    const double d = 2.0 + u;
+    const double rd = rcp_pos(d);
+    double s = u * rd;
+    s = __builtin_fma(__builtin_fma(-s, d, u), rd, s);
+    const double s2 = s * s;
+    double p = 1.0 / 11.0;
+    p = __builtin_fma(p, s2, 1.0 / 9.0);
+    p = __builtin_fma(p, s2, 1.0 / 7.0);
+    p = __builtin_fma(p, s2, 1.0 / 5.0);
+    p = __builtin_fma(p, s2, 1.0 / 3.0);
+    const double s2x = s + s;
+    return __builtin_fma(s2x * s2, p, s2x);
+}
+
+// ln|M w| at the start of a step, for the stage logs: within a step the
+// stage omegas stay close to omega_n, so ln|M w_s| = ln|M w_n| + ln(1 + u),
+// u = (w_s - w_n)/w_n, with a short series; |u| > 1/8 (rejected or very
+// long steps) falls back to the full log.
+struct LogBase {
+    double lnv;    // ln|M w_n|
+    double w;      // w_n
+    double iw;     // 1/w_n
+};
 
 // dy/dt of Eqs. (1)-(4) at y = (w, S1, S2, L).  Returns d omega/dt in d[0].
 //
 // With v = M w and x = v^{1/3}:
-//   d w/dt = K v^2 x^5 B,  B = 1 + x^2 (c2 + x (c3' + x (c4' + x (c5 + x (c6' + x c7)))))
-//     c3' = 4 pi - so1 L.S1 - so2 L.S2,  c4' = c4 - ss1 S1.S2 + ss2 (L.S1)(L.S2),
+//   d w/dt = K w^2 x^5 B,  B = 1 + x^2 (c2 + x (c3' + x (c4' + x (c5 + x (c6' + x c7)))))
+//     c3' = 4 pi - so1 L.S1 - so2 L.S2,
+//     c4' = c4 - ssd (247 S1.S2 - 721 (L.S1)(L.S2)),
 //     c6' = c6 - (1712/105) ln x;
-//   Omega_1 x S1 = p [ (g1 x^2 - 3 sig v L.S2) (L x S1) - sig v (S1 x S2) ],
-//   Omega_2 x S2 = p [ (g2 x^2 - 3 sig v L.S1) (L x S2) + sig v (S1 x S2) ],
-//     p = v/(2M) (Eq. (4) expanded; (M w)^2 (M w)^{-1/3} / (2M) = p x^2);
+//   Omega_1 x S1 = p [ (g1 x^2 - 3 sv L.S2) (L x S1) - sv (S1 x S2) ],
+//   Omega_2 x S2 = p [ (g2 x^2 - 3 sv L.S1) (L x S2) + sv (S1 x S2) ],
+//     p = w/2 = (M w)/(2M),  sv = w/M  (Eq. (4) expanded; the eta (M w)^{-1/3}
+//     term times (M w)^2/(2M) is p g_i x^2);
 //   dL/dt = -lam x (dS1/dt + dS2/dt)   (Eq. (3)).
 // Off the physical region (stage points of rejected or fixed steps) omega may
 // be negative; x is then the real cube root and the log term uses
 // ln(16 x^2) = ln 16 + (2/3) ln|v|, which is what Eq. (1) gives for any real x.
-template <class RowT>
-__device__ __forceinline__ void rhs(const RowT& r, const TermConsts& tc, const double* __restrict__ y,
-                                    double* __restrict__ d) {
-    const double v = r[R_M] * y[0];
+template <class RowT, bool FAST_LOG>
+__device__ __forceinline__ void rhs(const RowT& r, const TermConsts& tc, const LogBase& lb,
+                                    const double* __restrict__ y, double* __restrict__ d) {
+    const double w = y[0];
+    const double v = r[R_M] * w;
     const double x = cbrt_real(v);
-    const double lnx = log_pos(__builtin_fabs(v)) * (1.0 / 3.0);
+    double lnv;
+    if (FAST_LOG) {
+        const double u = (w - lb.w) * lb.iw;
+        if (__builtin_fabs(u) <= 0.125) lnv = lb.lnv + log1p_small(u);
+        else lnv = log_pos(__builtin_fabs(v));
+    } else {
+        lnv = log_pos(__builtin_fabs(v));
+    }
     const double x2 = x * x;
     const double L0 = y[7], L1 = y[8], L2 = y[9];
     const double a0 = y[1], a1 = y[2], a2 = y[3];   // S1
@@ -221,8 +253,9 @@ __device__ __forceinline__ void rhs(const RowT& r, const TermConsts& tc, const d
     const double S12 = __builtin_fma(a0, b0, __builtin_fma(a1, b1, a2 * b2));
 
     const double c3p = __builtin_fma(-r[R_SO2], LS2, __builtin_fma(-r[R_SO1], LS1, tc.c3));
-    const double c4p = __builtin_fma(r[R_SS2] * LS1, LS2, __builtin_fma(-r[R_SS1], S12, r[R_C4]));
-    const double c6p = __builtin_fma(tc.c6log, lnx, r[R_C6]);
+    const double ssb = __builtin_fma(247.0, S12, -721.0 * (LS1 * LS2));
+    const double c4p = __builtin_fma(-r[R_SSD], ssb, r[R_C4]);
+    const double c6p = __builtin_fma(tc.c6lnv, lnv, r[R_C6]);
     double B = __builtin_fma(x, r[R_C7], c6p);
     B = __builtin_fma(x, B, r[R_C5]);
     B = __builtin_fma(x, B, c4p);
@@ -230,10 +263,10 @@ __device__ __forceinline__ void rhs(const RowT& r, const TermConsts& tc, const d
     B = __builtin_fma(x, B, r[R_C2]);
     B = __builtin_fma(x2, B, 1.0);
     const double x5 = x2 * x2 * x;
-    d[0] = (r[R_K] * (v * v)) * x5 * B;
+    d[0] = (r[R_K] * (w * w)) * x5 * B;
 
-    const double p = v * r[R_HINVM];
-    const double sv = r[R_SIG] * v;
+    const double p = 0.5 * w;
+    const double sv = r[R_SIGM] * w;
     const double al1 = p * __builtin_fma(r[R_G1], x2, -3.0 * sv * LS2);
     const double al2 = p * __builtin_fma(r[R_G2], x2, -3.0 * sv * LS1);
     const double be = p * sv;
@@ -254,6 +287,16 @@ __device__ __forceinline__ void rhs(const RowT& r, const TermConsts& tc, const d
     d[7] = q * (d[1] + d[4]);
     d[8] = q * (d[2] + d[5]);
     d[9] = q * (d[3] + d[6]);
+}
+
+// the base of the stage logs at the state y
+template <class RowT>
+__device__ __forceinline__ LogBase log_base(const RowT& r, const double* y) {
+    LogBase lb;
+    lb.w = y[0];
+    lb.lnv = log_pos(__builtin_fabs(r[R_M] * y[0]));
+    lb.iw = 1.0 / y[0];
+    return lb;
 }
 
 }  // namespace pn

@@ -18,9 +18,22 @@
 #include "pn.h"
 #include "pn_device.hpp"
 
-// Occupancy the integration kernels are compiled for (waves per SIMD).
+// Build switches of the integration kernels (chosen by measurement):
+//   PN_WAVES_PER_EU  occupancy target, waves per SIMD
+//   PN_ROW_LDS       coefficient row in LDS (1) or in registers (0)
+//   PN_K2_LDS        second stage derivative parked in LDS (1) or registers (0)
+//   PN_FAST_LOG      stage logs from one log per step plus a short series (1)
 #ifndef PN_WAVES_PER_EU
 #define PN_WAVES_PER_EU 2
+#endif
+#ifndef PN_ROW_LDS
+#define PN_ROW_LDS 0
+#endif
+#ifndef PN_K2_LDS
+#define PN_K2_LDS 0
+#endif
+#ifndef PN_FAST_LOG
+#define PN_FAST_LOG 1
 #endif
 
 namespace pn {
@@ -73,7 +86,14 @@ struct Lane {
     double k1[10];
     double dt1;       // dt/d(variable) of k1: 1 in time mode, 1/omega-dot in omega mode
     double t, h;
+#if PN_ROW_LDS
     RowLds row;       // this lane's coefficient column in LDS
+#else
+    Row row;
+#endif
+#if PN_K2_LDS
+    volatile double* k2p;   // this lane's k2 column in LDS (entry c at k2p[c * 64])
+#endif
     int64_t idx;
     int acc, rej, nrhs;
     bool omega_mode, last_rej;
@@ -135,7 +155,8 @@ __device__ int load_lane(const Io& io, const Uni& u, Lane& L, int64_t idx) {
     if (bad) { write_out(io, u, L, PN_ST_BAD_INPUT); return PN_ST_BAD_INPUT; }
     if (!u.tend && !(L.y[0] < u.omega_f)) { write_out(io, u, L, PN_ST_DONE_AT_START); return PN_ST_DONE_AT_START; }
     make_row(L.row, m1, m2, u.terms, u.theta_literal);
-    rhs(L.row, u.tc, L.y, L.k1);
+    LogBase lb;
+    rhs<decltype(L.row), false>(L.row, u.tc, lb, L.y, L.k1);
     L.dt1 = 1.0;
     L.nrhs = 1;
     return 0;
@@ -160,34 +181,52 @@ __device__ __forceinline__ int step_lane(const Uni& u, Lane& L, bool any_w) {
         if (htry >= remain) { htry = remain; last = true; }
     }
 
-    const RowLds R = L.row;
+    const auto& R = L.row;
     const double* y = L.y;
     const double* k1 = L.k1;
-    double Y[10], k2[10], k3[10], k4[10], k5[10], k6[10];
+    double Y[10], k3[10], k4[10], k5[10], k6[10];
+#if PN_K2_LDS
+    double k2r[10];
+    volatile double* k2p = L.k2p;
+#define K2(c) k2p[(c) * 64]
+#else
+    double k2[10];
+#define K2(c) k2[c]
+#endif
     double dtj, dt7;
     double dts = B1 * L.dt1;     // sum_j b_j dt_j, used in omega mode only
+    LogBase lb;
+    if (PN_FAST_LOG) lb = log_base(R, y);
+    constexpr bool FL = PN_FAST_LOG != 0;
 
     const double h = htry;
     {
         const double c1 = h * A21;
 #pragma unroll
         for (int c = 0; c < 10; ++c) Y[c] = __builtin_fma(c1, k1[c], y[c]);
-        rhs(R, u.tc, Y, k2);
+#if PN_K2_LDS
+        rhs<decltype(L.row), FL>(R, u.tc, lb, Y, k2r);
+        if (any_w) to_omega_variable(k2r, dtj, L.omega_mode);
+#pragma unroll
+        for (int c = 0; c < 10; ++c) K2(c) = k2r[c];
+#else
+        rhs<decltype(L.row), FL>(R, u.tc, lb, Y, k2);
         if (any_w) to_omega_variable(k2, dtj, L.omega_mode);
+#endif
     }
     {
         const double c1 = h * A31, c2 = h * A32;
 #pragma unroll
-        for (int c = 0; c < 10; ++c) Y[c] = __builtin_fma(c2, k2[c], __builtin_fma(c1, k1[c], y[c]));
-        rhs(R, u.tc, Y, k3);
+        for (int c = 0; c < 10; ++c) Y[c] = __builtin_fma(c2, K2(c), __builtin_fma(c1, k1[c], y[c]));
+        rhs<decltype(L.row), FL>(R, u.tc, lb, Y, k3);
         if (any_w) { to_omega_variable(k3, dtj, L.omega_mode); dts = __builtin_fma(B3, dtj, dts); }
     }
     {
         const double c1 = h * A41, c2 = h * A42, c3 = h * A43;
 #pragma unroll
         for (int c = 0; c < 10; ++c)
-            Y[c] = __builtin_fma(c3, k3[c], __builtin_fma(c2, k2[c], __builtin_fma(c1, k1[c], y[c])));
-        rhs(R, u.tc, Y, k4);
+            Y[c] = __builtin_fma(c3, k3[c], __builtin_fma(c2, K2(c), __builtin_fma(c1, k1[c], y[c])));
+        rhs<decltype(L.row), FL>(R, u.tc, lb, Y, k4);
         if (any_w) { to_omega_variable(k4, dtj, L.omega_mode); dts = __builtin_fma(B4, dtj, dts); }
     }
     {
@@ -195,8 +234,8 @@ __device__ __forceinline__ int step_lane(const Uni& u, Lane& L, bool any_w) {
 #pragma unroll
         for (int c = 0; c < 10; ++c)
             Y[c] = __builtin_fma(c4, k4[c], __builtin_fma(c3, k3[c],
-                   __builtin_fma(c2, k2[c], __builtin_fma(c1, k1[c], y[c]))));
-        rhs(R, u.tc, Y, k5);
+                   __builtin_fma(c2, K2(c), __builtin_fma(c1, k1[c], y[c]))));
+        rhs<decltype(L.row), FL>(R, u.tc, lb, Y, k5);
         if (any_w) { to_omega_variable(k5, dtj, L.omega_mode); dts = __builtin_fma(B5, dtj, dts); }
     }
     {
@@ -204,10 +243,11 @@ __device__ __forceinline__ int step_lane(const Uni& u, Lane& L, bool any_w) {
 #pragma unroll
         for (int c = 0; c < 10; ++c)
             Y[c] = __builtin_fma(c5, k5[c], __builtin_fma(c4, k4[c], __builtin_fma(c3, k3[c],
-                   __builtin_fma(c2, k2[c], __builtin_fma(c1, k1[c], y[c])))));
-        rhs(R, u.tc, Y, k6);
+                   __builtin_fma(c2, K2(c), __builtin_fma(c1, k1[c], y[c])))));
+        rhs<decltype(L.row), FL>(R, u.tc, lb, Y, k6);
         if (any_w) { to_omega_variable(k6, dtj, L.omega_mode); dts = __builtin_fma(B6, dtj, dts); }
     }
+#undef K2
     // stage 7 point = 5th-order solution; the error sum over k1, k3..k6 is
     // formed now so that those vectors die before the last RHS
     double Ep[10];
@@ -222,7 +262,7 @@ __device__ __forceinline__ int step_lane(const Uni& u, Lane& L, bool any_w) {
         }
     }
     double k7[10];
-    rhs(R, u.tc, Y, k7);
+    rhs<decltype(L.row), FL>(R, u.tc, lb, Y, k7);
     dt7 = 1.0;
     if (any_w) to_omega_variable(k7, dt7, L.omega_mode);
     L.nrhs += 6;
@@ -303,10 +343,16 @@ __device__ __forceinline__ uint64_t wave_ballot(bool p) { return __ballot(p); }
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(PN_WAVES_PER_EU)))
 void integrate_persistent(Io io, Uni u, unsigned long long* counter) {
-    __shared__ double s_rows[BLOCK / 64][NROW][64];
     const int lane = lane_id();
     Lane L;
+#if PN_ROW_LDS
+    __shared__ double s_rows[BLOCK / 64][NROW][64];
     L.row.p = &s_rows[threadIdx.x / 64][0][lane];
+#endif
+#if PN_K2_LDS
+    __shared__ double s_k2[BLOCK / 64][10][64];
+    L.k2p = &s_k2[threadIdx.x / 64][0][lane];
+#endif
     L.idx = -1;
     bool active = false;
     bool exhausted = false;     // wave-uniform
@@ -359,10 +405,16 @@ void integrate_persistent(Io io, Uni u, unsigned long long* counter) {
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(PN_WAVES_PER_EU)))
 void integrate_static(Io io, Uni u) {
-    __shared__ double s_rows[BLOCK / 64][NROW][64];
     const int64_t idx = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
     Lane L;
+#if PN_ROW_LDS
+    __shared__ double s_rows[BLOCK / 64][NROW][64];
     L.row.p = &s_rows[threadIdx.x / 64][0][lane_id()];
+#endif
+#if PN_K2_LDS
+    __shared__ double s_k2[BLOCK / 64][10][64];
+    L.k2p = &s_k2[threadIdx.x / 64][0][lane_id()];
+#endif
     bool active = false;
     if (idx < u.n) active = load_lane(io, u, L, idx) == 0;
     for (;;) {
@@ -389,7 +441,8 @@ __global__ void rhs_kernel(int64_t n, int64_t ld, const double* __restrict__ m, 
     double yy[10], dd[10];
 #pragma unroll
     for (int c = 0; c < 10; ++c) yy[c] = y[c * ld + i];
-    rhs(r, tc, yy, dd);
+    LogBase lb;
+    rhs<Row, false>(r, tc, lb, yy, dd);
 #pragma unroll
     for (int c = 0; c < 10; ++c) d[c * ld + i] = dd[c];
 }
@@ -453,7 +506,7 @@ TermConsts term_consts(int terms) {
     TermConsts tc;
     const bool pn_on = (terms & PN_TERM_PN) != 0;
     tc.c3 = pn_on ? 4.0 * PN_PI : 0.0;
-    tc.c6log = pn_on ? -(1712.0 / 105.0) : 0.0;
+    tc.c6lnv = pn_on ? -(1712.0 / 315.0) : 0.0;
     return tc;
 }
 
