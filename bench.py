@@ -35,6 +35,9 @@ METRIC = "inspirals/s to ω_f at 1e-8 tol; RHS evals/s as % VALU peak; adjoint/f
 F_RHS = 134
 F_STEP_COMB = 704
 FP64_VECTOR_PEAK_TFLOPS = 78.6      # MI355X: 256 CU x 2.4 GHz x 128 FLOP/clk
+FP32_VECTOR_PEAK_TFLOPS = 157.3     # MI355X datasheet (counts packed FP32; packed FP32
+                                    # instructions are disabled in this build, so half of
+                                    # it is the reachable ceiling)
 HBM_PEAK_GBS = 8000.0
 
 
@@ -81,6 +84,8 @@ def main() -> int:
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--waves-per-simd", type=int, default=0)
     ap.add_argument("--refill-min", type=int, default=0)
+    ap.add_argument("--precision", default=None, choices=["fp64", "fp32split"],
+                    help="default: the workload's own precision")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     args = ap.parse_args()
@@ -100,7 +105,8 @@ def main() -> int:
     pop = population.generate(w)
     d = api.to_device(pop)
     out = api.alloc_outputs(pop["n"])
-    opts = api.make_opts(schedule=args.schedule, block=args.block,
+    precision = args.precision or w.precision
+    opts = api.make_opts(schedule=args.schedule, block=args.block, precision=precision,
                          waves_per_simd=args.waves_per_simd, refill_min=args.refill_min)
     stream = torch.cuda.current_stream()
 
@@ -132,6 +138,7 @@ def main() -> int:
         print(f"bench.py: non-OK statuses {bad}", file=sys.stderr)
     flops = algorithmic_flops(steps)
     achieved = flops / (avg_ms * 1e-3) / 1e12
+    peak = FP64_VECTOR_PEAK_TFLOPS if precision == "fp64" else FP32_VECTOR_PEAK_TFLOPS
     n = pop["n"]
     value = n * args.steps / wall
     res = {
@@ -145,13 +152,13 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if precision == "fp64" else "f32 stages + f64 state/control",
         "data": "synthetic",
         "config": {"workload": w.name, "n": n, "tol": w.tol, "omega0": list(w.omega0[1:]),
                    "omega_f": w.omega_f, "q": list(w.q[1:]), "chi": list(w.chi[1:]),
-                   "precision": "fp64", "schedule": args.schedule, "parallelism": "single GPU"},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
+                   "precision": precision, "schedule": args.schedule, "parallelism": "single GPU"},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak,
+                     "unit": "TFLOP/s", "frac": achieved / peak,
                      "traffic": None},
         "kernel_ms": avg_ms,
         "rhs_evals_per_s": float(steps[2].astype(np.int64).sum()) / (avg_ms * 1e-3),
@@ -160,6 +167,17 @@ def main() -> int:
         "rejected_steps": int(steps[1].astype(np.int64).sum()),
         "algorithmic_flop_per_launch": flops,
     }
+    if precision != "fp64":
+        # the same population in FP64 (untimed) as the reference for the error report
+        out64 = api.pn_integrate(d["m"], d["S"], d["L"], d["omega0"], pop["omega_f"], pop["tol"],
+                                 api.make_opts(), stream=stream)
+        torch.cuda.synchronize()
+        dd = np.abs(out["dots"].cpu().numpy() - out64["dots"].cpu().numpy())
+        res["error_vs_fp64"] = {
+            "quantity": ["S1h.S2h", "S1h.Lh", "S2h.Lh"],
+            "max": dd.max(axis=1).tolist(), "p99": np.percentile(dd, 99, axis=1).tolist(),
+            "t_rel_max": float(np.abs(out["t"].cpu().numpy() / out64["t"].cpu().numpy() - 1).max()),
+            "reference": "the FP64 GPU path on the whole population (itself within 1e-8 of the oracle)"}
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(pop, args.cpu_budget)
     print(json.dumps(res), flush=True)

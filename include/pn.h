@@ -67,6 +67,15 @@ extern "C" {
 #define PN_TERM_SS_PREC 32   /* the S_j - 3 (S_j . L_hat) L_hat part of Eq. (4) */
 #define PN_TERM_ALL     63
 
+/* ---- arithmetic ---------------------------------------------------------- */
+#define PN_PREC_FP64        0  /* everything in FP64 */
+#define PN_PREC_FP32_SPLIT  1  /* stages, right-hand sides, increments and error
+                                  estimate in FP32; state, t, h, error norm, step
+                                  control and the omega >= omega_f test in FP64
+                                  (the FP32 increment is added to the FP64 state);
+                                  the paper ran its GPU in single precision with a
+                                  few computations in double (Sec. III) */
+
 /* ---- scheduling -------------------------------------------------------- */
 #define PN_SCHED_PERSISTENT 0  /* resident grid; lanes take new inspirals as theirs finish */
 #define PN_SCHED_STATIC     1  /* one lane per inspiral, no refill */
@@ -83,10 +92,12 @@ typedef struct pn_opts {
                               expansion the paper cites); 1: the extra factor eta
                               exactly as printed in Eq. (1) */
     int32_t schedule;      /* PN_SCHED_* */
-    int32_t block;         /* threads per block, a multiple of 64 in [64, 1024]; 0 -> 256 */
-    int32_t waves_per_simd;/* persistent grid: waves per SIMD (1..8); 0 -> 2 */
+    int32_t block;         /* threads per block: 64, 128, 256 or 512; 0 -> 256 */
+    int32_t waves_per_simd;/* persistent grid: waves per SIMD (1..8); 0 -> the
+                              occupancy the kernel is compiled for (2 FP64, 3 FP32-split) */
     int32_t refill_min;    /* persistent: a wave refills once this many of its lanes
                               are idle (1..64); 0 -> 1 */
+    int32_t precision;     /* PN_PREC_*; 0 -> FP64 */
 } pn_opts;
 
 /*

@@ -19,8 +19,9 @@ STATUS = {0: "OK", 1: "DONE_AT_START", -1: "MAX_STEPS", -2: "H_UNDERFLOW", -3: "
 # term switches
 PN_TERM_PN, PN_TERM_SO_WDOT, PN_TERM_SS_WDOT, PN_TERM_RR = 1, 2, 4, 8
 PN_TERM_SO_PREC, PN_TERM_SS_PREC, PN_TERM_ALL = 16, 32, 63
-# schedules
+# schedules and arithmetic
 PN_SCHED_PERSISTENT, PN_SCHED_STATIC = 0, 1
+PN_PREC_FP64, PN_PREC_FP32_SPLIT = 0, 1
 
 EXPORTS = ("pn_integrate", "pn_rhs", "pn_observables", "pn_strerror", "pn_version")
 
@@ -37,6 +38,7 @@ class PnOpts(C.Structure):
         ("block", C.c_int32),
         ("waves_per_simd", C.c_int32),
         ("refill_min", C.c_int32),
+        ("precision", C.c_int32),
     ]
 
 

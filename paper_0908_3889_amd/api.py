@@ -16,6 +16,7 @@ from . import _lib
 from ._lib import PnOpts, check, load
 
 SCHEDULES = {"persistent": _lib.PN_SCHED_PERSISTENT, "static": _lib.PN_SCHED_STATIC}
+PRECISIONS = {"fp64": _lib.PN_PREC_FP64, "fp32split": _lib.PN_PREC_FP32_SPLIT}
 
 
 def _soa(t: torch.Tensor, comps: int, n: int, name: str, dtype=torch.float64) -> torch.Tensor:
@@ -43,12 +44,13 @@ def _stream(stream):
 
 def make_opts(*, h0=0.0, h_fixed=0.0, t_end=0.0, max_steps=0, terms=_lib.PN_TERM_ALL,
               theta_literal=0, schedule="persistent", block=0, waves_per_simd=0,
-              refill_min=0) -> PnOpts:
+              refill_min=0, precision="fp64") -> PnOpts:
     o = PnOpts()
     o.h0, o.h_fixed, o.t_end = float(h0), float(h_fixed), float(t_end)
     o.max_steps, o.terms, o.theta_literal = int(max_steps), int(terms), int(theta_literal)
     o.schedule = SCHEDULES[schedule] if isinstance(schedule, str) else int(schedule)
     o.block, o.waves_per_simd, o.refill_min = int(block), int(waves_per_simd), int(refill_min)
+    o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     return o
 
 

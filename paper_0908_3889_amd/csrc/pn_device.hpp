@@ -299,4 +299,84 @@ __device__ __forceinline__ LogBase log_base(const RowT& r, const double* y) {
     return lb;
 }
 
+// ---------------------------------------------------------------------------
+// FP32 right-hand side (the FP32-split mode): the same Eqs. (1)-(4) in single
+// precision, with the hardware FP32 log2/exp2/reciprocal.
+// ---------------------------------------------------------------------------
+struct RowF {
+    float v[NROW];
+    __device__ __forceinline__ float operator[](int i) const { return v[i]; }
+};
+
+__device__ __forceinline__ RowF to_f32(const Row& r) {
+    RowF f;
+#pragma unroll
+    for (int i = 0; i < NROW; ++i) f.v[i] = (float)r.v[i];
+    return f;
+}
+
+// real cube root in FP32: hardware seed and one Newton step (negative a ->
+// -cbrt|a|; the seed handles the whole float range except 0).
+__device__ __forceinline__ float cbrt_f32(float a) {
+    const float m = __builtin_fabsf(a);
+    float x = __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(m) * (1.0f / 3.0f));
+    const float t = __builtin_fmaf(x * x, x, -m);
+    x = __builtin_fmaf(-t, __builtin_amdgcn_rcpf(3.0f * x * x), x);
+    return __builtin_copysignf(x, a);
+}
+
+struct TermConstsF {
+    float c3;      // 4 pi (or 0)
+    float c6lnv;   // -1712/315 (or 0)
+};
+
+// Eqs. (1)-(4) in FP32, same expansion as rhs() above.
+__device__ __forceinline__ void rhs_f32(const RowF& r, const TermConstsF& tc, const float* __restrict__ y,
+                                        float* __restrict__ d) {
+    const float w = y[0];
+    const float v = r[R_M] * w;
+    const float x = cbrt_f32(v);
+    const float lnv = __builtin_amdgcn_logf(__builtin_fabsf(v)) * 0.69314718055994531f;
+    const float x2 = x * x;
+    const float L0 = y[7], L1 = y[8], L2 = y[9];
+    const float a0 = y[1], a1 = y[2], a2 = y[3];
+    const float b0 = y[4], b1 = y[5], b2 = y[6];
+    const float LS1 = __builtin_fmaf(L0, a0, __builtin_fmaf(L1, a1, L2 * a2));
+    const float LS2 = __builtin_fmaf(L0, b0, __builtin_fmaf(L1, b1, L2 * b2));
+    const float S12 = __builtin_fmaf(a0, b0, __builtin_fmaf(a1, b1, a2 * b2));
+    const float c3p = __builtin_fmaf(-r[R_SO2], LS2, __builtin_fmaf(-r[R_SO1], LS1, tc.c3));
+    const float ssb = __builtin_fmaf(247.0f, S12, -721.0f * (LS1 * LS2));
+    const float c4p = __builtin_fmaf(-r[R_SSD], ssb, r[R_C4]);
+    const float c6p = __builtin_fmaf(tc.c6lnv, lnv, r[R_C6]);
+    float B = __builtin_fmaf(x, r[R_C7], c6p);
+    B = __builtin_fmaf(x, B, r[R_C5]);
+    B = __builtin_fmaf(x, B, c4p);
+    B = __builtin_fmaf(x, B, c3p);
+    B = __builtin_fmaf(x, B, r[R_C2]);
+    B = __builtin_fmaf(x2, B, 1.0f);
+    const float x5 = x2 * x2 * x;
+    d[0] = (r[R_K] * (w * w)) * x5 * B;
+    const float p = 0.5f * w;
+    const float sv = r[R_SIGM] * w;
+    const float al1 = p * __builtin_fmaf(r[R_G1], x2, -3.0f * sv * LS2);
+    const float al2 = p * __builtin_fmaf(r[R_G2], x2, -3.0f * sv * LS1);
+    const float be = p * sv;
+    const float u0 = __builtin_fmaf(L1, a2, -L2 * a1), u1 = __builtin_fmaf(L2, a0, -L0 * a2),
+                u2 = __builtin_fmaf(L0, a1, -L1 * a0);
+    const float w0 = __builtin_fmaf(L1, b2, -L2 * b1), w1 = __builtin_fmaf(L2, b0, -L0 * b2),
+                w2 = __builtin_fmaf(L0, b1, -L1 * b0);
+    const float c0 = __builtin_fmaf(a1, b2, -a2 * b1), c1 = __builtin_fmaf(a2, b0, -a0 * b2),
+                cc2 = __builtin_fmaf(a0, b1, -a1 * b0);
+    d[1] = __builtin_fmaf(al1, u0, -be * c0);
+    d[2] = __builtin_fmaf(al1, u1, -be * c1);
+    d[3] = __builtin_fmaf(al1, u2, -be * cc2);
+    d[4] = __builtin_fmaf(al2, w0, be * c0);
+    d[5] = __builtin_fmaf(al2, w1, be * c1);
+    d[6] = __builtin_fmaf(al2, w2, be * cc2);
+    const float q = -r[R_LAM] * x;
+    d[7] = q * (d[1] + d[4]);
+    d[8] = q * (d[2] + d[5]);
+    d[9] = q * (d[3] + d[6]);
+}
+
 }  // namespace pn

@@ -7,33 +7,29 @@
 // persistent grid in which a wave hands new inspirals to its idle lanes
 // (ballot + one atomic add per wave) so that inspirals of very different
 // lengths share lanes without leaving them idle.
+//
+// Two precisions share the scheduling code through a policy:
+//   F64       everything in FP64;
+//   F32Split  stages, right-hand sides, increments and error estimate in
+//             FP32; the state, t, h, the error norm, the step control and
+//             the omega >= omega_f test in FP64 (each FP32 increment is added
+//             to the FP64 state, so rounding does not build up in the state).
 #include <hip/hip_runtime.h>
 
 #include <atomic>
-#include <cstdio>
 #include <cstring>
 #include <mutex>
-#include <vector>
 
 #include "pn.h"
 #include "pn_device.hpp"
 
-// Build switches of the integration kernels (chosen by measurement):
-//   PN_WAVES_PER_EU  occupancy target, waves per SIMD
-//   PN_ROW_LDS       coefficient row in LDS (1) or in registers (0)
-//   PN_K2_LDS        second stage derivative parked in LDS (1) or registers (0)
-//   PN_FAST_LOG      stage logs from one log per step plus a short series (1)
-#ifndef PN_WAVES_PER_EU
-#define PN_WAVES_PER_EU 2
+// Occupancy targets (waves per SIMD) the integration kernels are compiled
+// for; chosen by measurement (register budget 512/target per lane).
+#ifndef PN_WPE_F64
+#define PN_WPE_F64 2
 #endif
-#ifndef PN_ROW_LDS
-#define PN_ROW_LDS 0
-#endif
-#ifndef PN_K2_LDS
-#define PN_K2_LDS 0
-#endif
-#ifndef PN_FAST_LOG
-#define PN_FAST_LOG 1
+#ifndef PN_WPE_F32
+#define PN_WPE_F32 3
 #endif
 
 namespace pn {
@@ -61,6 +57,7 @@ constexpr double Z_ACCEPT = 1.0 + 2.220446049250313e-16;
 struct Uni {
     double omega_f, tol, h0, h_fixed, t_end;
     TermConsts tc;
+    TermConstsF tcf;
     int64_t n, ld, max_steps;
     int terms, theta_literal;
     int fixed, tend;
@@ -80,47 +77,19 @@ struct Io {
     double* __restrict__ dots;
 };
 
-// Everything one lane carries for its current inspiral.
-struct Lane {
-    double y[10];
-    double k1[10];
-    double dt1;       // dt/d(variable) of k1: 1 in time mode, 1/omega-dot in omega mode
-    double t, h;
-#if PN_ROW_LDS
-    RowLds row;       // this lane's coefficient column in LDS
-#else
-    Row row;
-#endif
-#if PN_K2_LDS
-    volatile double* k2p;   // this lane's k2 column in LDS (entry c at k2p[c * 64])
-#endif
-    int64_t idx;
-    int acc, rej, nrhs;
-    bool omega_mode, last_rej;
-};
-
 __device__ __forceinline__ bool finite(double v) { return __builtin_isfinite(v); }
 
-// omega-mode: divide the RHS by omega-dot and put 1 in the omega slot.
-__device__ __forceinline__ void to_omega_variable(double* k, double& dt, bool om) {
-    const double s = om ? 1.0 / k[0] : 1.0;
+__device__ void write_out(const Io& io, const Uni& u, int64_t i, const double* y, double t, int acc,
+                          int rej, int nrhs, int st) {
+    const int64_t ld = u.ld;
 #pragma unroll
-    for (int c = 1; c < 10; ++c) k[c] *= s;
-    k[0] = om ? 1.0 : k[0];
-    dt = s;
-}
-
-__device__ void write_out(const Io& io, const Uni& u, const Lane& L, int st) {
-    const int64_t i = L.idx, ld = u.ld;
-#pragma unroll
-    for (int c = 0; c < 10; ++c) io.y[c * ld + i] = L.y[c];
-    io.t[i] = L.t;
-    io.steps[i] = L.acc;
-    io.steps[ld + i] = L.rej;
-    io.steps[2 * ld + i] = L.nrhs;
+    for (int c = 0; c < 10; ++c) io.y[c * ld + i] = y[c];
+    io.t[i] = t;
+    io.steps[i] = acc;
+    io.steps[ld + i] = rej;
+    io.steps[2 * ld + i] = nrhs;
     io.status[i] = st;
     if (io.dots) {
-        const double* y = L.y;
         const double n1 = __builtin_sqrt(y[1] * y[1] + y[2] * y[2] + y[3] * y[3]);
         const double n2 = __builtin_sqrt(y[4] * y[4] + y[5] * y[5] + y[6] * y[6]);
         const double nl = __builtin_sqrt(y[7] * y[7] + y[8] * y[8] + y[9] * y[9]);
@@ -133,226 +102,422 @@ __device__ void write_out(const Io& io, const Uni& u, const Lane& L, int st) {
     }
 }
 
-// Load inspiral idx into the lane and evaluate k1.  Returns 0 when the lane
-// now integrates it, or a status when it is finished at once (bad input, or
-// omega0 >= omega_f), in which case the outputs are already written.
-__device__ int load_lane(const Io& io, const Uni& u, Lane& L, int64_t idx) {
+// Read inspiral idx into y and the masses; returns 0, or the status of an
+// inspiral that is finished at once (bad input, or omega0 >= omega_f), whose
+// outputs are then already written.
+__device__ int read_input(const Io& io, const Uni& u, int64_t idx, double* y, double& m1, double& m2) {
     const int64_t ld = u.ld;
-    L.idx = idx;
-    const double m1 = io.m[idx], m2 = io.m[ld + idx];
-    L.y[0] = io.w0[idx];
+    m1 = io.m[idx];
+    m2 = io.m[ld + idx];
+    y[0] = io.w0[idx];
 #pragma unroll
-    for (int c = 0; c < 6; ++c) L.y[1 + c] = io.S0[c * ld + idx];
+    for (int c = 0; c < 6; ++c) y[1 + c] = io.S0[c * ld + idx];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) L.y[7 + c] = io.L0[c * ld + idx];
-    L.t = 0.0;
-    L.acc = 0; L.rej = 0; L.nrhs = 0;
-    L.omega_mode = false; L.last_rej = false;
-    L.h = u.fixed ? u.h_fixed : u.h0;
-    bool bad = !(m1 > 0.0) || !(m2 > 0.0) || !(L.y[0] > 0.0) || !finite(m1) || !finite(m2);
+    for (int c = 0; c < 3; ++c) y[7 + c] = io.L0[c * ld + idx];
+    bool bad = !(m1 > 0.0) || !(m2 > 0.0) || !(y[0] > 0.0) || !finite(m1) || !finite(m2);
 #pragma unroll
-    for (int c = 0; c < 10; ++c) bad = bad || !finite(L.y[c]);
-    if (bad) { write_out(io, u, L, PN_ST_BAD_INPUT); return PN_ST_BAD_INPUT; }
-    if (!u.tend && !(L.y[0] < u.omega_f)) { write_out(io, u, L, PN_ST_DONE_AT_START); return PN_ST_DONE_AT_START; }
-    make_row(L.row, m1, m2, u.terms, u.theta_literal);
-    LogBase lb;
-    rhs<decltype(L.row), false>(L.row, u.tc, lb, L.y, L.k1);
-    L.dt1 = 1.0;
-    L.nrhs = 1;
+    for (int c = 0; c < 10; ++c) bad = bad || !finite(y[c]);
+    if (bad) { write_out(io, u, idx, y, 0.0, 0, 0, 0, PN_ST_BAD_INPUT); return PN_ST_BAD_INPUT; }
+    if (!u.tend && !(y[0] < u.omega_f)) {
+        write_out(io, u, idx, y, 0.0, 0, 0, 0, PN_ST_DONE_AT_START);
+        return PN_ST_DONE_AT_START;
+    }
     return 0;
 }
 
-// One attempted Dormand-Prince step of an active lane.  Returns 0 while the
-// inspiral continues, 1 when it ended normally (PN_ST_OK), or a negative
-// status.  `any_w` is true when some lane of the wave is in omega mode.
-__device__ __forceinline__ int step_lane(const Uni& u, Lane& L, bool any_w) {
-    // guards at the start of a step
-    if (L.acc + L.rej >= u.max_steps) return PN_ST_MAX_STEPS;
-    if (!L.omega_mode && u.rr_on && L.k1[0] <= 0.0) return PN_ST_OMEGADOT_NONPOSITIVE;
-    if (L.omega_mode && L.dt1 <= 0.0) return PN_ST_OMEGADOT_NONPOSITIVE;
-
-    double htry = L.h;
-    bool last = false;
-    if (L.omega_mode) {
-        const double remain = u.omega_f - L.y[0];
-        if (htry >= remain) { htry = remain; last = true; }
-    } else if (u.tend) {
-        const double remain = u.t_end - L.t;
-        if (htry >= remain) { htry = remain; last = true; }
-    }
-
-    const auto& R = L.row;
-    const double* y = L.y;
-    const double* k1 = L.k1;
-    double Y[10], k3[10], k4[10], k5[10], k6[10];
-#if PN_K2_LDS
-    double k2r[10];
-    volatile double* k2p = L.k2p;
-#define K2(c) k2p[(c) * 64]
-#else
-    double k2[10];
-#define K2(c) k2[c]
-#endif
-    double dtj, dt7;
-    double dts = B1 * L.dt1;     // sum_j b_j dt_j, used in omega mode only
-    LogBase lb;
-    if (PN_FAST_LOG) lb = log_base(R, y);
-    constexpr bool FL = PN_FAST_LOG != 0;
-
-    const double h = htry;
-    {
-        const double c1 = h * A21;
-#pragma unroll
-        for (int c = 0; c < 10; ++c) Y[c] = __builtin_fma(c1, k1[c], y[c]);
-#if PN_K2_LDS
-        rhs<decltype(L.row), FL>(R, u.tc, lb, Y, k2r);
-        if (any_w) to_omega_variable(k2r, dtj, L.omega_mode);
-#pragma unroll
-        for (int c = 0; c < 10; ++c) K2(c) = k2r[c];
-#else
-        rhs<decltype(L.row), FL>(R, u.tc, lb, Y, k2);
-        if (any_w) to_omega_variable(k2, dtj, L.omega_mode);
-#endif
-    }
-    {
-        const double c1 = h * A31, c2 = h * A32;
-#pragma unroll
-        for (int c = 0; c < 10; ++c) Y[c] = __builtin_fma(c2, K2(c), __builtin_fma(c1, k1[c], y[c]));
-        rhs<decltype(L.row), FL>(R, u.tc, lb, Y, k3);
-        if (any_w) { to_omega_variable(k3, dtj, L.omega_mode); dts = __builtin_fma(B3, dtj, dts); }
-    }
-    {
-        const double c1 = h * A41, c2 = h * A42, c3 = h * A43;
-#pragma unroll
-        for (int c = 0; c < 10; ++c)
-            Y[c] = __builtin_fma(c3, k3[c], __builtin_fma(c2, K2(c), __builtin_fma(c1, k1[c], y[c])));
-        rhs<decltype(L.row), FL>(R, u.tc, lb, Y, k4);
-        if (any_w) { to_omega_variable(k4, dtj, L.omega_mode); dts = __builtin_fma(B4, dtj, dts); }
-    }
-    {
-        const double c1 = h * A51, c2 = h * A52, c3 = h * A53, c4 = h * A54;
-#pragma unroll
-        for (int c = 0; c < 10; ++c)
-            Y[c] = __builtin_fma(c4, k4[c], __builtin_fma(c3, k3[c],
-                   __builtin_fma(c2, K2(c), __builtin_fma(c1, k1[c], y[c]))));
-        rhs<decltype(L.row), FL>(R, u.tc, lb, Y, k5);
-        if (any_w) { to_omega_variable(k5, dtj, L.omega_mode); dts = __builtin_fma(B5, dtj, dts); }
-    }
-    {
-        const double c1 = h * A61, c2 = h * A62, c3 = h * A63, c4 = h * A64, c5 = h * A65;
-#pragma unroll
-        for (int c = 0; c < 10; ++c)
-            Y[c] = __builtin_fma(c5, k5[c], __builtin_fma(c4, k4[c], __builtin_fma(c3, k3[c],
-                   __builtin_fma(c2, K2(c), __builtin_fma(c1, k1[c], y[c])))));
-        rhs<decltype(L.row), FL>(R, u.tc, lb, Y, k6);
-        if (any_w) { to_omega_variable(k6, dtj, L.omega_mode); dts = __builtin_fma(B6, dtj, dts); }
-    }
-#undef K2
-    // stage 7 point = 5th-order solution; the error sum over k1, k3..k6 is
-    // formed now so that those vectors die before the last RHS
-    double Ep[10];
-    {
-        const double c1 = h * B1, c3 = h * B3, c4 = h * B4, c5 = h * B5, c6 = h * B6;
-#pragma unroll
-        for (int c = 0; c < 10; ++c) {
-            Y[c] = __builtin_fma(c6, k6[c], __builtin_fma(c5, k5[c], __builtin_fma(c4, k4[c],
-                   __builtin_fma(c3, k3[c], __builtin_fma(c1, k1[c], y[c])))));
-            Ep[c] = __builtin_fma(E6, k6[c], __builtin_fma(E5, k5[c], __builtin_fma(E4, k4[c],
-                    __builtin_fma(E3, k3[c], E1 * k1[c]))));
-        }
-    }
-    double k7[10];
-    rhs<decltype(L.row), FL>(R, u.tc, lb, Y, k7);
-    dt7 = 1.0;
-    if (any_w) to_omega_variable(k7, dt7, L.omega_mode);
-    L.nrhs += 6;
-
-    // error norm: z = err^2 = mean_c (e_c / (tol + tol max(|y_c|, |y5_c|)))^2
+// error norm z = err^2 = mean_c (e_c / (tol + tol max(|y_c|, |ynew_c|)))^2
+__device__ __forceinline__ double error_norm(const Uni& u, const double* y, const double* ynew, const double* e) {
     double z = 0.0;
-    bool fin = true;
-    if (!u.fixed) {
 #pragma unroll
-        for (int c = 0; c < 10; ++c) {
-            const double e = h * __builtin_fma(E7, k7[c], Ep[c]);
-            const double sc = __builtin_fma(u.tol, __builtin_fmax(__builtin_fabs(y[c]), __builtin_fabs(Y[c])), u.tol);
-            const double q = e * rcp_pos(sc);
-            z = __builtin_fma(q, q, z);
-        }
-        z *= 0.1;
-        fin = !__builtin_isnan(z);
+    for (int c = 0; c < 10; ++c) {
+        const double sc = __builtin_fma(u.tol, __builtin_fmax(__builtin_fabs(y[c]), __builtin_fabs(ynew[c])), u.tol);
+        const double q = e[c] * rcp_pos(sc);
+        z = __builtin_fma(q, q, z);
     }
-#pragma unroll
-    for (int c = 0; c < 10; ++c) fin = fin && finite(Y[c]);
-    if (!fin) return PN_ST_NONFINITE;
+    return z * 0.1;
+}
 
-    if (u.fixed || z <= Z_ACCEPT) {
-        if (!L.omega_mode && !u.tend && Y[0] > u.omega_f) {
-            // the candidate passes omega_f: discard it and finish the stretch
-            // with omega as the independent variable
-            L.omega_mode = true;
-            const double s = 1.0 / L.k1[0];
+// step factor after an accepted step with error z (safety 0.9, exponent 1/5,
+// clamped to [0.2, 5], no growth right after a rejection)
+__device__ __forceinline__ double accept_factor(double z, bool last_rej) {
+    const double zc = __builtin_fmin(__builtin_fmax(z, 9.313225746154785e-10), 1.073741824e9);
+    double fac = __builtin_fmin(5.0, __builtin_fmax(0.2, 0.9 * pow_m_tenth(zc)));
+    return last_rej ? __builtin_fmin(fac, 1.0) : fac;
+}
+
+__device__ __forceinline__ double reject_factor(double z) {
+    return __builtin_fmax(0.2, 0.9 * pow_m_tenth(__builtin_fmin(z, 1.073741824e9)));
+}
+
+// omega-mode: divide the RHS by omega-dot and put 1 in the omega slot.
+template <class T>
+__device__ __forceinline__ void to_omega_variable(T* k, T& dt, bool om) {
+    const T s = om ? T(1) / k[0] : T(1);
 #pragma unroll
-            for (int c = 1; c < 10; ++c) L.k1[c] *= s;
-            L.k1[0] = 1.0;
-            L.dt1 = s;
-            L.h = u.omega_f - L.y[0];
-            L.last_rej = false;
-            return 0;
-        }
-        if (L.omega_mode) {
-            L.t = __builtin_fma(h, dts, L.t);
-        } else {
-            L.t += h;
-        }
-#pragma unroll
-        for (int c = 0; c < 10; ++c) { L.y[c] = Y[c]; L.k1[c] = k7[c]; }
-        L.dt1 = dt7;
-        L.acc += 1;
-        if (!L.omega_mode && !u.tend && L.y[0] == u.omega_f) last = true;
-        if (last) {
-            if (L.omega_mode) L.y[0] = u.omega_f;
-            return 1;
-        }
-        if (!u.fixed) {
-            const double zc = __builtin_fmin(__builtin_fmax(z, 9.313225746154785e-10), 1.073741824e9);
-            double fac = 0.9 * pow_m_tenth(zc);
-            fac = __builtin_fmin(5.0, __builtin_fmax(0.2, fac));
-            if (L.last_rej) fac = __builtin_fmin(fac, 1.0);
-            L.h = h * fac;
-            L.last_rej = false;
-        }
+    for (int c = 1; c < 10; ++c) k[c] *= s;
+    k[0] = om ? T(1) : k[0];
+    dt = s;
+}
+
+// ===========================================================================
+// FP64 lane
+// ===========================================================================
+struct LaneF64 {
+    double y[10];
+    double k1[10];
+    double dt1;       // dt/d(variable) of k1: 1 in time mode, 1/omega-dot in omega mode
+    double t, h;
+    Row row;
+    int64_t idx;
+    int acc, rej, nrhs;
+    bool omega_mode, last_rej;
+};
+
+struct F64 {
+    using LaneT = LaneF64;
+
+    static __device__ int load(const Io& io, const Uni& u, LaneT& L, int64_t idx) {
+        L.idx = idx;
+        double m1, m2;
+        const int st = read_input(io, u, idx, L.y, m1, m2);
+        if (st) return st;
+        L.t = 0.0;
+        L.acc = 0; L.rej = 0;
+        L.omega_mode = false; L.last_rej = false;
+        L.h = u.fixed ? u.h_fixed : u.h0;
+        make_row(L.row, m1, m2, u.terms, u.theta_literal);
+        LogBase lb;
+        rhs<Row, false>(L.row, u.tc, lb, L.y, L.k1);
+        L.dt1 = 1.0;
+        L.nrhs = 1;
         return 0;
     }
-    // rejected
-    L.rej += 1;
-    const double zc = __builtin_fmin(z, 1.073741824e9);
-    const double fac = __builtin_fmax(0.2, 0.9 * pow_m_tenth(zc));
-    L.h = h * fac;
-    L.last_rej = true;
-    const double scale = L.omega_mode ? __builtin_fabs(L.y[0]) : __builtin_fmax(1.0, __builtin_fabs(L.t));
-    if (L.h < 1e-14 * scale) return PN_ST_H_UNDERFLOW;
-    return 0;
-}
 
+    static __device__ void finish(const Io& io, const Uni& u, const LaneT& L, int st) {
+        write_out(io, u, L.idx, L.y, L.t, L.acc, L.rej, L.nrhs, st);
+    }
+
+    // One attempted step; 0 = continue, 1 = finished OK, < 0 = status.
+    static __device__ __forceinline__ int step(const Uni& u, LaneT& L, bool any_w) {
+        if (L.acc + L.rej >= u.max_steps) return PN_ST_MAX_STEPS;
+        if (!L.omega_mode && u.rr_on && L.k1[0] <= 0.0) return PN_ST_OMEGADOT_NONPOSITIVE;
+        if (L.omega_mode && L.dt1 <= 0.0) return PN_ST_OMEGADOT_NONPOSITIVE;
+
+        double h = L.h;
+        bool last = false;
+        if (L.omega_mode) {
+            const double remain = u.omega_f - L.y[0];
+            if (h >= remain) { h = remain; last = true; }
+        } else if (u.tend) {
+            const double remain = u.t_end - L.t;
+            if (h >= remain) { h = remain; last = true; }
+        }
+
+        const Row& R = L.row;
+        const double* y = L.y;
+        const double* k1 = L.k1;
+        double Y[10], k2[10], k3[10], k4[10], k5[10], k6[10];
+        double dtj;
+        double dts = B1 * L.dt1;     // sum_j b_j dt_j, used in omega mode only
+        const LogBase lb = log_base(R, y);
+        {
+            const double c1 = h * A21;
+#pragma unroll
+            for (int c = 0; c < 10; ++c) Y[c] = __builtin_fma(c1, k1[c], y[c]);
+            rhs<Row, true>(R, u.tc, lb, Y, k2);
+            if (any_w) to_omega_variable(k2, dtj, L.omega_mode);
+        }
+        {
+            const double c1 = h * A31, c2 = h * A32;
+#pragma unroll
+            for (int c = 0; c < 10; ++c) Y[c] = __builtin_fma(c2, k2[c], __builtin_fma(c1, k1[c], y[c]));
+            rhs<Row, true>(R, u.tc, lb, Y, k3);
+            if (any_w) { to_omega_variable(k3, dtj, L.omega_mode); dts = __builtin_fma(B3, dtj, dts); }
+        }
+        {
+            const double c1 = h * A41, c2 = h * A42, c3 = h * A43;
+#pragma unroll
+            for (int c = 0; c < 10; ++c)
+                Y[c] = __builtin_fma(c3, k3[c], __builtin_fma(c2, k2[c], __builtin_fma(c1, k1[c], y[c])));
+            rhs<Row, true>(R, u.tc, lb, Y, k4);
+            if (any_w) { to_omega_variable(k4, dtj, L.omega_mode); dts = __builtin_fma(B4, dtj, dts); }
+        }
+        {
+            const double c1 = h * A51, c2 = h * A52, c3 = h * A53, c4 = h * A54;
+#pragma unroll
+            for (int c = 0; c < 10; ++c)
+                Y[c] = __builtin_fma(c4, k4[c], __builtin_fma(c3, k3[c],
+                       __builtin_fma(c2, k2[c], __builtin_fma(c1, k1[c], y[c]))));
+            rhs<Row, true>(R, u.tc, lb, Y, k5);
+            if (any_w) { to_omega_variable(k5, dtj, L.omega_mode); dts = __builtin_fma(B5, dtj, dts); }
+        }
+        {
+            const double c1 = h * A61, c2 = h * A62, c3 = h * A63, c4 = h * A64, c5 = h * A65;
+#pragma unroll
+            for (int c = 0; c < 10; ++c)
+                Y[c] = __builtin_fma(c5, k5[c], __builtin_fma(c4, k4[c], __builtin_fma(c3, k3[c],
+                       __builtin_fma(c2, k2[c], __builtin_fma(c1, k1[c], y[c])))));
+            rhs<Row, true>(R, u.tc, lb, Y, k6);
+            if (any_w) { to_omega_variable(k6, dtj, L.omega_mode); dts = __builtin_fma(B6, dtj, dts); }
+        }
+        // stage 7 point = 5th-order solution; the error sum over k1, k3..k6 is
+        // formed now so that those vectors die before the last RHS
+        double Ep[10];
+        {
+            const double c1 = h * B1, c3 = h * B3, c4 = h * B4, c5 = h * B5, c6 = h * B6;
+#pragma unroll
+            for (int c = 0; c < 10; ++c) {
+                Y[c] = __builtin_fma(c6, k6[c], __builtin_fma(c5, k5[c], __builtin_fma(c4, k4[c],
+                       __builtin_fma(c3, k3[c], __builtin_fma(c1, k1[c], y[c])))));
+                Ep[c] = __builtin_fma(E6, k6[c], __builtin_fma(E5, k5[c], __builtin_fma(E4, k4[c],
+                        __builtin_fma(E3, k3[c], E1 * k1[c]))));
+            }
+        }
+        double k7[10], dt7 = 1.0;
+        rhs<Row, true>(R, u.tc, lb, Y, k7);
+        if (any_w) to_omega_variable(k7, dt7, L.omega_mode);
+        L.nrhs += 6;
+
+        double z = 0.0;
+        bool fin = true;
+        if (!u.fixed) {
+            double e[10];
+#pragma unroll
+            for (int c = 0; c < 10; ++c) e[c] = h * __builtin_fma(E7, k7[c], Ep[c]);
+            z = error_norm(u, y, Y, e);
+            fin = !__builtin_isnan(z);
+        }
+#pragma unroll
+        for (int c = 0; c < 10; ++c) fin = fin && finite(Y[c]);
+        if (!fin) return PN_ST_NONFINITE;
+
+        if (u.fixed || z <= Z_ACCEPT) {
+            if (!L.omega_mode && !u.tend && Y[0] > u.omega_f) {
+                // the candidate passes omega_f: discard it and finish the stretch
+                // with omega as the independent variable
+                L.omega_mode = true;
+                const double s = 1.0 / L.k1[0];
+#pragma unroll
+                for (int c = 1; c < 10; ++c) L.k1[c] *= s;
+                L.k1[0] = 1.0;
+                L.dt1 = s;
+                L.h = u.omega_f - L.y[0];
+                L.last_rej = false;
+                return 0;
+            }
+            L.t = L.omega_mode ? __builtin_fma(h, dts, L.t) : L.t + h;
+#pragma unroll
+            for (int c = 0; c < 10; ++c) { L.y[c] = Y[c]; L.k1[c] = k7[c]; }
+            L.dt1 = dt7;
+            L.acc += 1;
+            if (!L.omega_mode && !u.tend && L.y[0] == u.omega_f) last = true;
+            if (last) {
+                if (L.omega_mode) L.y[0] = u.omega_f;
+                return 1;
+            }
+            if (!u.fixed) {
+                L.h = h * accept_factor(z, L.last_rej);
+                L.last_rej = false;
+            }
+            return 0;
+        }
+        L.rej += 1;
+        L.h = h * reject_factor(z);
+        L.last_rej = true;
+        const double scale = L.omega_mode ? __builtin_fabs(L.y[0]) : __builtin_fmax(1.0, __builtin_fabs(L.t));
+        if (L.h < 1e-14 * scale) return PN_ST_H_UNDERFLOW;
+        return 0;
+    }
+};
+
+// ===========================================================================
+// FP32-split lane
+// ===========================================================================
+struct LaneF32 {
+    double y[10];     // state, FP64
+    float k1[10];     // FSAL derivative, FP32
+    float dt1;
+    double t, h;
+    RowF row;
+    int64_t idx;
+    int acc, rej, nrhs;
+    bool omega_mode, last_rej;
+};
+
+struct F32Split {
+    using LaneT = LaneF32;
+
+    static __device__ int load(const Io& io, const Uni& u, LaneT& L, int64_t idx) {
+        L.idx = idx;
+        double m1, m2;
+        const int st = read_input(io, u, idx, L.y, m1, m2);
+        if (st) return st;
+        L.t = 0.0;
+        L.acc = 0; L.rej = 0;
+        L.omega_mode = false; L.last_rej = false;
+        L.h = u.fixed ? u.h_fixed : u.h0;
+        Row r;
+        make_row(r, m1, m2, u.terms, u.theta_literal);
+        L.row = to_f32(r);
+        float yf[10];
+#pragma unroll
+        for (int c = 0; c < 10; ++c) yf[c] = (float)L.y[c];
+        rhs_f32(L.row, u.tcf, yf, L.k1);
+        L.dt1 = 1.0f;
+        L.nrhs = 1;
+        return 0;
+    }
+
+    static __device__ void finish(const Io& io, const Uni& u, const LaneT& L, int st) {
+        write_out(io, u, L.idx, L.y, L.t, L.acc, L.rej, L.nrhs, st);
+    }
+
+    static __device__ __forceinline__ int step(const Uni& u, LaneT& L, bool any_w) {
+        if (L.acc + L.rej >= u.max_steps) return PN_ST_MAX_STEPS;
+        if (!L.omega_mode && u.rr_on && L.k1[0] <= 0.0f) return PN_ST_OMEGADOT_NONPOSITIVE;
+        if (L.omega_mode && L.dt1 <= 0.0f) return PN_ST_OMEGADOT_NONPOSITIVE;
+
+        double h = L.h;
+        bool last = false;
+        if (L.omega_mode) {
+            const double remain = u.omega_f - L.y[0];
+            if (h >= remain) { h = remain; last = true; }
+        } else if (u.tend) {
+            const double remain = u.t_end - L.t;
+            if (h >= remain) { h = remain; last = true; }
+        }
+
+        const RowF& R = L.row;
+        const float* k1 = L.k1;
+        const float hf = (float)h;
+        float yf[10], Y[10], k2[10], k3[10], k4[10], k5[10], k6[10];
+#pragma unroll
+        for (int c = 0; c < 10; ++c) yf[c] = (float)L.y[c];
+        float dtj;
+        float dts = (float)B1 * L.dt1;
+        {
+            const float c1 = hf * (float)A21;
+#pragma unroll
+            for (int c = 0; c < 10; ++c) Y[c] = __builtin_fmaf(c1, k1[c], yf[c]);
+            rhs_f32(R, u.tcf, Y, k2);
+            if (any_w) to_omega_variable(k2, dtj, L.omega_mode);
+        }
+        {
+            const float c1 = hf * (float)A31, c2 = hf * (float)A32;
+#pragma unroll
+            for (int c = 0; c < 10; ++c) Y[c] = __builtin_fmaf(c2, k2[c], __builtin_fmaf(c1, k1[c], yf[c]));
+            rhs_f32(R, u.tcf, Y, k3);
+            if (any_w) { to_omega_variable(k3, dtj, L.omega_mode); dts = __builtin_fmaf((float)B3, dtj, dts); }
+        }
+        {
+            const float c1 = hf * (float)A41, c2 = hf * (float)A42, c3 = hf * (float)A43;
+#pragma unroll
+            for (int c = 0; c < 10; ++c)
+                Y[c] = __builtin_fmaf(c3, k3[c], __builtin_fmaf(c2, k2[c], __builtin_fmaf(c1, k1[c], yf[c])));
+            rhs_f32(R, u.tcf, Y, k4);
+            if (any_w) { to_omega_variable(k4, dtj, L.omega_mode); dts = __builtin_fmaf((float)B4, dtj, dts); }
+        }
+        {
+            const float c1 = hf * (float)A51, c2 = hf * (float)A52, c3 = hf * (float)A53, c4 = hf * (float)A54;
+#pragma unroll
+            for (int c = 0; c < 10; ++c)
+                Y[c] = __builtin_fmaf(c4, k4[c], __builtin_fmaf(c3, k3[c],
+                       __builtin_fmaf(c2, k2[c], __builtin_fmaf(c1, k1[c], yf[c]))));
+            rhs_f32(R, u.tcf, Y, k5);
+            if (any_w) { to_omega_variable(k5, dtj, L.omega_mode); dts = __builtin_fmaf((float)B5, dtj, dts); }
+        }
+        {
+            const float c1 = hf * (float)A61, c2 = hf * (float)A62, c3 = hf * (float)A63, c4 = hf * (float)A64,
+                        c5 = hf * (float)A65;
+#pragma unroll
+            for (int c = 0; c < 10; ++c)
+                Y[c] = __builtin_fmaf(c5, k5[c], __builtin_fmaf(c4, k4[c], __builtin_fmaf(c3, k3[c],
+                       __builtin_fmaf(c2, k2[c], __builtin_fmaf(c1, k1[c], yf[c])))));
+            rhs_f32(R, u.tcf, Y, k6);
+            if (any_w) { to_omega_variable(k6, dtj, L.omega_mode); dts = __builtin_fmaf((float)B6, dtj, dts); }
+        }
+        // 5th-order increment D (FP32), the stage-7 point, and the error sum
+        float D[10], Ep[10];
+#pragma unroll
+        for (int c = 0; c < 10; ++c) {
+            D[c] = hf * __builtin_fmaf((float)B6, k6[c], __builtin_fmaf((float)B5, k5[c],
+                        __builtin_fmaf((float)B4, k4[c], __builtin_fmaf((float)B3, k3[c], (float)B1 * k1[c]))));
+            Y[c] = yf[c] + D[c];
+            Ep[c] = __builtin_fmaf((float)E6, k6[c], __builtin_fmaf((float)E5, k5[c],
+                    __builtin_fmaf((float)E4, k4[c], __builtin_fmaf((float)E3, k3[c], (float)E1 * k1[c]))));
+        }
+        float k7[10], dt7 = 1.0f;
+        rhs_f32(R, u.tcf, Y, k7);
+        if (any_w) to_omega_variable(k7, dt7, L.omega_mode);
+        L.nrhs += 6;
+
+        // candidate state in FP64
+        double ynew[10];
+#pragma unroll
+        for (int c = 0; c < 10; ++c) ynew[c] = L.y[c] + (double)D[c];
+        double z = 0.0;
+        bool fin = true;
+        if (!u.fixed) {
+            double e[10];
+#pragma unroll
+            for (int c = 0; c < 10; ++c) e[c] = (double)(hf * __builtin_fmaf((float)E7, k7[c], Ep[c]));
+            z = error_norm(u, L.y, ynew, e);
+            fin = !__builtin_isnan(z);
+        }
+#pragma unroll
+        for (int c = 0; c < 10; ++c) fin = fin && finite(ynew[c]) && __builtin_isfinite(k7[c]);
+        if (!fin) return PN_ST_NONFINITE;
+
+        if (u.fixed || z <= Z_ACCEPT) {
+            if (!L.omega_mode && !u.tend && ynew[0] > u.omega_f) {
+                L.omega_mode = true;
+                const float s = 1.0f / L.k1[0];
+#pragma unroll
+                for (int c = 1; c < 10; ++c) L.k1[c] *= s;
+                L.k1[0] = 1.0f;
+                L.dt1 = s;
+                L.h = u.omega_f - L.y[0];
+                L.last_rej = false;
+                return 0;
+            }
+            L.t = L.omega_mode ? __builtin_fma(h, (double)dts, L.t) : L.t + h;
+#pragma unroll
+            for (int c = 0; c < 10; ++c) { L.y[c] = ynew[c]; L.k1[c] = k7[c]; }
+            L.dt1 = dt7;
+            L.acc += 1;
+            if (!L.omega_mode && !u.tend && L.y[0] == u.omega_f) last = true;
+            if (last) {
+                if (L.omega_mode) L.y[0] = u.omega_f;
+                return 1;
+            }
+            if (!u.fixed) {
+                L.h = h * accept_factor(z, L.last_rej);
+                L.last_rej = false;
+            }
+            return 0;
+        }
+        L.rej += 1;
+        L.h = h * reject_factor(z);
+        L.last_rej = true;
+        const double scale = L.omega_mode ? __builtin_fabs(L.y[0]) : __builtin_fmax(1.0, __builtin_fabs(L.t));
+        if (L.h < 1e-14 * scale) return PN_ST_H_UNDERFLOW;
+        return 0;
+    }
+};
+
+// ===========================================================================
+// Scheduling
+// ===========================================================================
 __device__ __forceinline__ int lane_id() { return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u)); }
 
 __device__ __forceinline__ uint64_t wave_ballot(bool p) { return __ballot(p); }
 
-// Persistent kernel: each wave loops, handing new inspirals to idle lanes
-// from a global counter, until the counter passes n and its lanes are done.
-template <int BLOCK>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(PN_WAVES_PER_EU)))
-void integrate_persistent(Io io, Uni u, unsigned long long* counter) {
+// Persistent loop: each wave hands new inspirals to idle lanes from a global
+// counter, until the counter passes n and its lanes are done.
+template <class P>
+__device__ __forceinline__ void persistent_loop(const Io& io, const Uni& u, unsigned long long* counter) {
     const int lane = lane_id();
-    Lane L;
-#if PN_ROW_LDS
-    __shared__ double s_rows[BLOCK / 64][NROW][64];
-    L.row.p = &s_rows[threadIdx.x / 64][0][lane];
-#endif
-#if PN_K2_LDS
-    __shared__ double s_k2[BLOCK / 64][10][64];
-    L.k2p = &s_k2[threadIdx.x / 64][0][lane];
-#endif
+    typename P::LaneT L;
     L.idx = -1;
     bool active = false;
     bool exhausted = false;     // wave-uniform
@@ -360,8 +525,8 @@ void integrate_persistent(Io io, Uni u, unsigned long long* counter) {
         // ---- refill idle lanes --------------------------------------------------
         if (!exhausted) {
             uint64_t need = wave_ballot(!active);
-            const int nactive = 64 - __popcll(need);
-            if (need != 0 && (__popcll(need) >= u.refill_min || nactive == 0)) {
+            const int nidle = __popcll(need);
+            if (need != 0 && (nidle >= u.refill_min || nidle == 64)) {
                 while (need != 0 && !exhausted) {
                     const int cnt = __popcll(need);
                     const int leader = __ffsll((unsigned long long)need) - 1;
@@ -376,7 +541,7 @@ void integrate_persistent(Io io, Uni u, unsigned long long* counter) {
                                               __builtin_amdgcn_mbcnt_lo((unsigned)need, 0u));
                         const unsigned long long idx = base + rank;
                         if (idx < (unsigned long long)u.n) {
-                            const int st = load_lane(io, u, L, (int64_t)idx);
+                            const int st = P::load(io, u, L, (int64_t)idx);
                             if (st == 0) active = true; else still = true;
                         }
                     }
@@ -392,9 +557,9 @@ void integrate_persistent(Io io, Uni u, unsigned long long* counter) {
         // ---- one step on every active lane ----------------------------------------
         const bool any_w = wave_ballot(active && L.omega_mode) != 0;
         if (active) {
-            const int r = step_lane(u, L, any_w);
+            const int r = P::step(u, L, any_w);
             if (r != 0) {
-                write_out(io, u, L, r == 1 ? PN_ST_OK : r);
+                P::finish(io, u, L, r == 1 ? PN_ST_OK : r);
                 active = false;
             }
         }
@@ -402,32 +567,46 @@ void integrate_persistent(Io io, Uni u, unsigned long long* counter) {
 }
 
 // One lane per inspiral, no refill: a wave runs until its longest inspiral ends.
-template <int BLOCK>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(PN_WAVES_PER_EU)))
-void integrate_static(Io io, Uni u) {
-    const int64_t idx = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-    Lane L;
-#if PN_ROW_LDS
-    __shared__ double s_rows[BLOCK / 64][NROW][64];
-    L.row.p = &s_rows[threadIdx.x / 64][0][lane_id()];
-#endif
-#if PN_K2_LDS
-    __shared__ double s_k2[BLOCK / 64][10][64];
-    L.k2p = &s_k2[threadIdx.x / 64][0][lane_id()];
-#endif
+template <class P>
+__device__ __forceinline__ void static_loop(const Io& io, const Uni& u, int64_t idx) {
+    typename P::LaneT L;
     bool active = false;
-    if (idx < u.n) active = load_lane(io, u, L, idx) == 0;
+    if (idx < u.n) active = P::load(io, u, L, idx) == 0;
     for (;;) {
         if (wave_ballot(active) == 0) break;
         const bool any_w = wave_ballot(active && L.omega_mode) != 0;
         if (active) {
-            const int r = step_lane(u, L, any_w);
+            const int r = P::step(u, L, any_w);
             if (r != 0) {
-                write_out(io, u, L, r == 1 ? PN_ST_OK : r);
+                P::finish(io, u, L, r == 1 ? PN_ST_OK : r);
                 active = false;
             }
         }
     }
+}
+
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(PN_WPE_F64)))
+void integrate_persistent_f64(Io io, Uni u, unsigned long long* counter) {
+    persistent_loop<F64>(io, u, counter);
+}
+
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(PN_WPE_F32)))
+void integrate_persistent_f32s(Io io, Uni u, unsigned long long* counter) {
+    persistent_loop<F32Split>(io, u, counter);
+}
+
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(PN_WPE_F64)))
+void integrate_static_f64(Io io, Uni u) {
+    static_loop<F64>(io, u, (int64_t)blockIdx.x * BLOCK + threadIdx.x);
+}
+
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(PN_WPE_F32)))
+void integrate_static_f32s(Io io, Uni u) {
+    static_loop<F32Split>(io, u, (int64_t)blockIdx.x * BLOCK + threadIdx.x);
 }
 
 __global__ void reset_counter(unsigned long long* c) { *c = 0ull; }
@@ -471,7 +650,7 @@ __global__ void observables_kernel(int64_t n, int64_t ld, const double* __restri
 constexpr int kCounterSlots = 1024;
 
 struct DevCtx {
-    bool ready = false;
+    std::atomic<bool> ready{false};
     int cus = 0;
     unsigned long long* counters = nullptr;   // kCounterSlots work counters
     std::atomic<unsigned> next{0};
@@ -485,9 +664,9 @@ int get_ctx(DevCtx** out) {
     int dev = -1;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return PN_ENODEV;
     DevCtx& c = g_ctx[dev];
-    if (!c.ready) {
+    if (!c.ready.load(std::memory_order_acquire)) {
         std::lock_guard<std::mutex> lk(g_ctx_mu);
-        if (!c.ready) {
+        if (!c.ready.load(std::memory_order_relaxed)) {
             hipDeviceProp_t prop;
             if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return PN_ENODEV;
             if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return PN_ENODEV;
@@ -495,7 +674,7 @@ int get_ctx(DevCtx** out) {
             void* p = nullptr;
             if (hipMalloc(&p, sizeof(unsigned long long) * kCounterSlots) != hipSuccess) return PN_ENOMEM;
             c.counters = (unsigned long long*)p;
-            c.ready = true;
+            c.ready.store(true, std::memory_order_release);
         }
     }
     *out = &c;
@@ -511,11 +690,13 @@ TermConsts term_consts(int terms) {
 }
 
 template <int BLOCK>
-hipError_t launch_forward(const Io& io, const Uni& u, int schedule, int waves_per_simd, int cus,
+hipError_t launch_forward(const Io& io, const Uni& u, int precision, int schedule, int waves_per_simd, int cus,
                           unsigned long long* counter, hipStream_t s) {
+    const bool f32 = precision == PN_PREC_FP32_SPLIT;
     if (schedule == PN_SCHED_STATIC) {
         const int64_t grid = (u.n + BLOCK - 1) / BLOCK;
-        hipLaunchKernelGGL(integrate_static<BLOCK>, dim3((unsigned)grid), dim3(BLOCK), 0, s, io, u);
+        if (f32) hipLaunchKernelGGL(integrate_static_f32s<BLOCK>, dim3((unsigned)grid), dim3(BLOCK), 0, s, io, u);
+        else hipLaunchKernelGGL(integrate_static_f64<BLOCK>, dim3((unsigned)grid), dim3(BLOCK), 0, s, io, u);
         return hipGetLastError();
     }
     hipLaunchKernelGGL(reset_counter, dim3(1), dim3(1), 0, s, counter);
@@ -525,7 +706,10 @@ hipError_t launch_forward(const Io& io, const Uni& u, int schedule, int waves_pe
     int64_t waves = (int64_t)cus * 4 * waves_per_simd;
     if (waves > waves_needed) waves = waves_needed;
     const int64_t grid = (waves * 64 + BLOCK - 1) / BLOCK;
-    hipLaunchKernelGGL(integrate_persistent<BLOCK>, dim3((unsigned)grid), dim3(BLOCK), 0, s, io, u, counter);
+    if (f32)
+        hipLaunchKernelGGL(integrate_persistent_f32s<BLOCK>, dim3((unsigned)grid), dim3(BLOCK), 0, s, io, u, counter);
+    else
+        hipLaunchKernelGGL(integrate_persistent_f64<BLOCK>, dim3((unsigned)grid), dim3(BLOCK), 0, s, io, u, counter);
     return hipGetLastError();
 }
 
@@ -546,7 +730,7 @@ const char* pn_strerror(int code) {
     }
 }
 
-const char* pn_version(void) { return "pn-gfx950 0.1"; }
+const char* pn_version(void) { return "pn-gfx950 0.2"; }
 
 int pn_integrate(int64_t n, int64_t ld, const double* m, const double* S0, const double* L0,
                  const double* omega0, double omega_f, double tol, const pn_opts* opt,
@@ -560,14 +744,17 @@ int pn_integrate(int64_t n, int64_t ld, const double* m, const double* S0, const
     const bool fixed = o.h_fixed > 0.0;
     const bool tend = o.t_end > 0.0;
     if (o.h_fixed < 0.0 || !(o.h_fixed == o.h_fixed) || !(o.t_end == o.t_end) || o.t_end < 0.0) return PN_EINVAL;
+    if (fixed && !(o.h_fixed < 1e300)) return PN_EINVAL;
     if (!fixed && !(tol > 0.0 && tol < 1e300)) return PN_EINVAL;
     if (!tend && !(omega_f > 0.0 && omega_f < 1e300)) return PN_EINVAL;
     if (tend && !(o.t_end < 1e300)) return PN_EINVAL;
     if (!(o.h0 == o.h0) || o.h0 >= 1e300) return PN_EINVAL;
     if (o.schedule != PN_SCHED_PERSISTENT && o.schedule != PN_SCHED_STATIC) return PN_EINVAL;
+    if (o.precision != PN_PREC_FP64 && o.precision != PN_PREC_FP32_SPLIT) return PN_EINVAL;
     const int block = o.block ? o.block : 256;
-    if (block != 64 && block != 128 && block != 256 && block != 512 && block != 1024) return PN_EINVAL;
-    const int wps = o.waves_per_simd ? o.waves_per_simd : 2;
+    if (block != 64 && block != 128 && block != 256 && block != 512) return PN_EINVAL;
+    const int wps = o.waves_per_simd ? o.waves_per_simd
+                                     : (o.precision == PN_PREC_FP32_SPLIT ? PN_WPE_F32 : PN_WPE_F64);
     if (wps < 1 || wps > 8) return PN_EINVAL;
     const int refill = o.refill_min ? o.refill_min : 1;
     if (refill < 1 || refill > 64) return PN_EINVAL;
@@ -588,6 +775,8 @@ int pn_integrate(int64_t n, int64_t ld, const double* m, const double* S0, const
     u.terms = o.terms > 0 ? o.terms : PN_TERM_ALL;
     u.theta_literal = o.theta_literal;
     u.tc = term_consts(u.terms);
+    u.tcf.c3 = (float)u.tc.c3;
+    u.tcf.c6lnv = (float)u.tc.c6lnv;
     u.n = n;
     u.ld = ld;
     u.max_steps = o.max_steps > 0 ? o.max_steps : 10000000LL;
@@ -604,11 +793,10 @@ int pn_integrate(int64_t n, int64_t ld, const double* m, const double* S0, const
     hipStream_t s = (hipStream_t)stream;
     hipError_t e;
     switch (block) {
-        case 64: e = launch_forward<64>(io, u, o.schedule, wps, ctx->cus, counter, s); break;
-        case 128: e = launch_forward<128>(io, u, o.schedule, wps, ctx->cus, counter, s); break;
-        case 512: e = launch_forward<512>(io, u, o.schedule, wps, ctx->cus, counter, s); break;
-        case 1024: e = launch_forward<1024>(io, u, o.schedule, wps, ctx->cus, counter, s); break;
-        default: e = launch_forward<256>(io, u, o.schedule, wps, ctx->cus, counter, s); break;
+        case 64: e = launch_forward<64>(io, u, o.precision, o.schedule, wps, ctx->cus, counter, s); break;
+        case 128: e = launch_forward<128>(io, u, o.precision, o.schedule, wps, ctx->cus, counter, s); break;
+        case 512: e = launch_forward<512>(io, u, o.precision, o.schedule, wps, ctx->cus, counter, s); break;
+        default: e = launch_forward<256>(io, u, o.precision, o.schedule, wps, ctx->cus, counter, s); break;
     }
     return e == hipSuccess ? PN_OK : PN_EHIP;
 }

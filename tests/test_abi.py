@@ -44,8 +44,13 @@ def test_strerror_and_version(lib):
 
 def test_opts_struct_layout_matches_header():
     from paper_0908_3889_amd._lib import PnOpts
-    # 3 doubles, one int64, six int32
-    assert C.sizeof(PnOpts) == 3 * 8 + 8 + 6 * 4
+    # 3 doubles, one int64, seven int32, padded to 8 bytes
+    assert C.sizeof(PnOpts) == 3 * 8 + 8 + 7 * 4 + 4
+    names = [f[0] for f in PnOpts._fields_]
+    src = open(os.path.join(ROOT, "include", "pn.h")).read()
+    body = src[src.index("typedef struct pn_opts"):src.index("} pn_opts;")]
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    assert re.findall(r"\b(\w+);", body) == names
 
 
 def test_invalid_arguments_return_einval_without_a_device(lib):
@@ -68,6 +73,8 @@ def test_invalid_arguments_return_einval_without_a_device(lib):
     bad = PnOpts(); bad.h_fixed = -1.0
     assert call(10, 10, opt=bad) == PN_EINVAL
     bad = PnOpts(); bad.terms = 64
+    assert call(10, 10, opt=bad) == PN_EINVAL
+    bad = PnOpts(); bad.precision = 2
     assert call(10, 10, opt=bad) == PN_EINVAL
     assert call(0, 0) == PN_OK                       # empty batch: nothing to do
     assert lib.pn_rhs(-1, 0, fake, fake, fake, None, z) == PN_EINVAL
