@@ -57,6 +57,7 @@ extern "C" {
 #define PN_ST_NONFINITE            -3  /* NaN error estimate or non-finite candidate state */
 #define PN_ST_BAD_INPUT            -4  /* m_i <= 0, omega0 <= 0 or a non-finite input */
 #define PN_ST_OMEGADOT_NONPOSITIVE -5  /* d omega/dt <= 0 at the start of a step */
+#define PN_ST_TAPE_FULL            -6  /* pn_integrate_record: more accepted steps than cap_steps */
 
 /* ---- which terms of Eqs. (1)-(4) are on (bitmask) --------------------- */
 #define PN_TERM_PN       1   /* non-spinning corrections of Eq. (1), (M w)^{2/3} ... (M w)^{7/3} */
@@ -145,6 +146,53 @@ int pn_rhs(int64_t n, int64_t ld, const double* m, const double* y, double* dydt
  * each 0 where one of the norms is 0.
  */
 int pn_observables(int64_t n, int64_t ld, const double* y, double* dots, void* stream);
+
+/*
+ * The discrete adjoint.
+ *
+ * pn_integrate_record -- pn_integrate (FP64, omega_f termination) that also
+ * writes, per inspiral i, a tape of pn_tape_stride(cap_steps, ckpt_every)
+ * doubles at tape + i * stride: [n_t, n_w, h_0 .. h_{cap-1}, y(0), y(K),
+ * y(2K), ...] -- the number of accepted time steps and omega-steps, every
+ * accepted step size, and the state every K = ckpt_every accepted steps.
+ * An inspiral with more than cap_steps accepted steps ends with status
+ * PN_ST_TAPE_FULL.  tape is a device buffer of n * stride doubles (caller
+ * owned).  Other arguments as pn_integrate; opt->precision must be FP64 and
+ * opt->t_end 0.
+ */
+size_t pn_tape_stride(int64_t cap_steps, int32_t ckpt_every);
+int pn_integrate_record(int64_t n, int64_t ld,
+                        const double* m, const double* S0, const double* L0, const double* omega0,
+                        double omega_f, double tol, const pn_opts* opt,
+                        double* y_final, double* t_final, int32_t* steps, int32_t* status,
+                        double* dots, double* tape, int64_t cap_steps, int32_t ckpt_every,
+                        void* stream);
+
+/*
+ * pn_integrate_adjoint -- reverse-mode derivative of the recorded integration
+ * with the accepted step sizes held fixed (the discrete adjoint of the
+ * Dormand-Prince map that produced y_final, t_final).  For the loss
+ *   L = sum_i gy_final[:, i] . y_final[:, i] + gt_final[i] t_final[i]
+ * it writes dL/dm [2][ld], dL/dS0 [6][ld], dL/dL0 [3][ld], dL/domega0 [ld].
+ * The last omega-step ends on omega_f, so its size depends on the state and
+ * the final omega carries no derivative.
+ *   m, tape, cap_steps, ckpt_every, status: the inputs and outputs of the
+ *     pn_integrate_record call (same masses, same opt->terms/theta_literal);
+ *   gy_final [10][ld], gt_final [ld] (may be NULL = 0);
+ *   workspace: device buffer of at least pn_adjoint_workspace_bytes(n, K)
+ *     bytes (the replayed states of one checkpoint segment per inspiral);
+ *   order: optional device permutation of [0, n) giving the order in which
+ *     inspirals are assigned to lanes (e.g. sorted by step count, so that a
+ *     wave's lanes run segments of equal length); NULL = identity.
+ * Inspirals with status DONE_AT_START get the identity (dL/dS0 = gy, ...,
+ * dL/dm = 0); any other non-OK status gets NaN.
+ */
+size_t pn_adjoint_workspace_bytes(int64_t n, int32_t ckpt_every);
+int pn_integrate_adjoint(int64_t n, int64_t ld, const double* m, double omega_f, const pn_opts* opt,
+                         const double* tape, int64_t cap_steps, int32_t ckpt_every,
+                         const int32_t* status, const double* gy_final, const double* gt_final,
+                         double* g_m, double* g_S0, double* g_L0, double* g_omega0,
+                         double* workspace, size_t ws_bytes, const int32_t* order, void* stream);
 
 /* Name of a PN_* return code (static string). */
 const char* pn_strerror(int code);

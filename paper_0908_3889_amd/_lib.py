@@ -15,7 +15,8 @@ LIB_PATH = os.environ.get("PN_LIB") or os.path.join(HERE, "libpn.so")
 PN_OK, PN_EINVAL, PN_ENODEV, PN_EHIP, PN_ENOMEM = 0, -1, -2, -3, -4
 # per-inspiral status
 STATUS = {0: "OK", 1: "DONE_AT_START", -1: "MAX_STEPS", -2: "H_UNDERFLOW", -3: "NONFINITE",
-          -4: "BAD_INPUT", -5: "OMEGADOT_NONPOSITIVE"}
+          -4: "BAD_INPUT", -5: "OMEGADOT_NONPOSITIVE", -6: "TAPE_FULL"}
+PN_ST_TAPE_FULL = -6
 # term switches
 PN_TERM_PN, PN_TERM_SO_WDOT, PN_TERM_SS_WDOT, PN_TERM_RR = 1, 2, 4, 8
 PN_TERM_SO_PREC, PN_TERM_SS_PREC, PN_TERM_ALL = 16, 32, 63
@@ -23,7 +24,9 @@ PN_TERM_SO_PREC, PN_TERM_SS_PREC, PN_TERM_ALL = 16, 32, 63
 PN_SCHED_PERSISTENT, PN_SCHED_STATIC = 0, 1
 PN_PREC_FP64, PN_PREC_FP32_SPLIT = 0, 1
 
-EXPORTS = ("pn_integrate", "pn_rhs", "pn_observables", "pn_strerror", "pn_version")
+EXPORTS = ("pn_integrate", "pn_rhs", "pn_observables", "pn_strerror", "pn_version",
+           "pn_tape_stride", "pn_integrate_record", "pn_adjoint_workspace_bytes",
+           "pn_integrate_adjoint")
 
 
 class PnOpts(C.Structure):
@@ -70,6 +73,16 @@ def load():
     L.pn_strerror.restype = C.c_char_p
     L.pn_version.argtypes = []
     L.pn_version.restype = C.c_char_p
+    L.pn_tape_stride.argtypes = [i64, C.c_int32]
+    L.pn_tape_stride.restype = C.c_size_t
+    L.pn_integrate_record.argtypes = [i64, i64, vp, vp, vp, vp, dbl, dbl, popts, vp, vp, vp, vp, vp,
+                                      vp, i64, C.c_int32, vp]
+    L.pn_integrate_record.restype = C.c_int
+    L.pn_adjoint_workspace_bytes.argtypes = [i64, C.c_int32]
+    L.pn_adjoint_workspace_bytes.restype = C.c_size_t
+    L.pn_integrate_adjoint.argtypes = [i64, i64, vp, dbl, popts, vp, i64, C.c_int32, vp, vp, vp, vp, vp,
+                                       vp, vp, vp, C.c_size_t, vp, vp]
+    L.pn_integrate_adjoint.restype = C.c_int
     _lib = L
     return L
 

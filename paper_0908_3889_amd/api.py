@@ -98,6 +98,103 @@ def pn_integrate(m, S0, L0, omega0, omega_f, tol, opts: PnOpts | None = None, ou
     return out
 
 
+def _check_inputs(m, S0, L0, omega0):
+    n = int(omega0.shape[0])
+    _soa(omega0, 1, n, "omega0")
+    for t, c, name in ((m, 2, "m"), (S0, 6, "S0"), (L0, 3, "L0")):
+        _soa(t, c, n, name)
+        if n > 0 and _ld(t, n) != n:
+            raise ValueError(f"{name} must be contiguous")
+    return n
+
+
+def pn_tape_stride(cap_steps: int, ckpt_every: int) -> int:
+    return int(load().pn_tape_stride(int(cap_steps), int(ckpt_every)))
+
+
+def pn_integrate_record(m, S0, L0, omega0, omega_f, tol, opts: PnOpts | None = None, *,
+                        cap_steps: int = 4096, ckpt_every: int = 64, stream=None) -> dict:
+    """pn_integrate that also writes the tape the adjoint replays (contiguous
+    inputs).  Returns the outputs of pn_integrate plus 'tape' [n, stride]."""
+    n = _check_inputs(m, S0, L0, omega0)
+    out = alloc_outputs(n, omega0.device, True)
+    stride = pn_tape_stride(cap_steps, ckpt_every)
+    tape = torch.empty((n, stride), dtype=torch.float64, device=omega0.device)
+    o = opts if opts is not None else make_opts()
+    p = lambda t: C.c_void_p(t.data_ptr())
+    rc = load().pn_integrate_record(n, n, p(m), p(S0), p(L0), p(omega0), float(omega_f), float(tol),
+                                    C.byref(o), p(out["y"]), p(out["t"]), p(out["steps"]),
+                                    p(out["status"]), p(out["dots"]), p(tape), int(cap_steps),
+                                    int(ckpt_every), _stream(stream))
+    check(rc, "pn_integrate_record")
+    out.update(tape=tape, cap_steps=int(cap_steps), ckpt_every=int(ckpt_every))
+    return out
+
+
+def pn_integrate_adjoint(m, omega_f, rec: dict, gy, gt=None, opts: PnOpts | None = None,
+                         order=None, stream=None) -> dict:
+    """Gradients of sum(gy * y_final) + sum(gt * t_final) with respect to
+    m [2, n], S0 [6, n], L0 [3, n], omega0 [n], for the recorded run `rec`
+    (the dict returned by pn_integrate_record)."""
+    n = int(rec["status"].shape[0])
+    _soa(m, 2, n, "m"); _soa(gy, 10, n, "gy")
+    if gt is not None:
+        _soa(gt, 1, n, "gt")
+    if order is not None:
+        _soa(order, 1, n, "order", torch.int32)
+    K = rec["ckpt_every"]
+    dev = m.device
+    ws_bytes = int(load().pn_adjoint_workspace_bytes(n, K))
+    ws = torch.empty(max(ws_bytes // 8, 1), dtype=torch.float64, device=dev)
+    g = {"m": torch.empty((2, n), dtype=torch.float64, device=dev),
+         "S0": torch.empty((6, n), dtype=torch.float64, device=dev),
+         "L0": torch.empty((3, n), dtype=torch.float64, device=dev),
+         "omega0": torch.empty((n,), dtype=torch.float64, device=dev)}
+    o = opts if opts is not None else make_opts()
+    p = lambda t: C.c_void_p(t.data_ptr()) if t is not None else None
+    rc = load().pn_integrate_adjoint(n, n, p(m), float(omega_f), C.byref(o), p(rec["tape"]),
+                                     rec["cap_steps"], K, p(rec["status"]), p(gy), p(gt), p(g["m"]),
+                                     p(g["S0"]), p(g["L0"]), p(g["omega0"]), p(ws), ws_bytes, p(order),
+                                     _stream(stream))
+    check(rc, "pn_integrate_adjoint")
+    return g
+
+
+class PNIntegrate(torch.autograd.Function):
+    """y_final, t_final = PNIntegrate.apply(m, S0, L0, omega0, omega_f, tol, ckpt_every, cap_steps)
+
+    Forward: the recorded FP64 integration.  Backward: the discrete adjoint
+    with the accepted step sizes held fixed.  Inputs contiguous on the GPU.
+    A run that needs more than cap_steps accepted steps is repeated with a
+    doubled cap."""
+
+    @staticmethod
+    def forward(ctx, m, S0, L0, omega0, omega_f, tol, ckpt_every=64, cap_steps=2048):
+        m, S0, L0, omega0 = (t.detach().contiguous() for t in (m, S0, L0, omega0))
+        cap = int(cap_steps)
+        while True:
+            rec = pn_integrate_record(m, S0, L0, omega0, omega_f, tol, cap_steps=cap,
+                                      ckpt_every=int(ckpt_every))
+            if not bool((rec["status"] == _lib.PN_ST_TAPE_FULL).any()):
+                break
+            cap *= 2
+        ctx.rec = rec
+        ctx.omega_f = float(omega_f)
+        ctx.save_for_backward(m)
+        ctx.mark_non_differentiable(rec["status"], rec["steps"])
+        return rec["y"], rec["t"], rec["status"], rec["steps"]
+
+    @staticmethod
+    def backward(ctx, gy, gt, _gs, _gst):
+        (m,) = ctx.saved_tensors
+        rec = ctx.rec
+        gy = torch.zeros_like(rec["y"]) if gy is None else gy.contiguous()
+        gt = None if gt is None else gt.contiguous()
+        order = torch.argsort(rec["steps"][0], descending=True).to(torch.int32)
+        g = pn_integrate_adjoint(m, ctx.omega_f, rec, gy, gt, order=order)
+        return g["m"], g["S0"], g["L0"], g["omega0"], None, None, None, None
+
+
 def pn_rhs(m, y, opts: PnOpts | None = None, stream=None) -> torch.Tensor:
     """Eqs. (1)-(4) pointwise: m [2, n], y [10, n] -> dy/dt [10, n]."""
     n = int(y.shape[1])

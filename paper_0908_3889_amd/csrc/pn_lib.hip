@@ -21,6 +21,7 @@
 #include <mutex>
 
 #include "pn.h"
+#include "pn_adjoint.hpp"
 #include "pn_device.hpp"
 
 // Occupancy targets (waves per SIMD) the integration kernels are compiled
@@ -63,6 +64,11 @@ struct Uni {
     int fixed, tend;
     int refill_min;
     int rr_on;
+    // tape for the adjoint: per inspiral, [n_t, n_w, h_0 .. h_{cap-1},
+    // checkpoints y(step jK), j = 0 .. cap/K] (doubles, `tape_stride` apart)
+    double* tape;
+    int64_t tape_stride;
+    int tape_cap, ckpt_every;
 };
 
 struct Io {
@@ -170,9 +176,19 @@ struct LaneF64 {
     Row row;
     int64_t idx;
     int acc, rej, nrhs;
+    int nt;           // accepted time steps (recording only)
     bool omega_mode, last_rej;
 };
 
+__device__ __forceinline__ double* tape_of(const Uni& u, int64_t idx) { return u.tape + idx * u.tape_stride; }
+
+__device__ __forceinline__ void tape_checkpoint(const Uni& u, int64_t idx, int j, const double* y) {
+    double* ck = tape_of(u, idx) + 2 + u.tape_cap + (int64_t)j * 10;
+#pragma unroll
+    for (int c = 0; c < 10; ++c) ck[c] = y[c];
+}
+
+template <bool RECORD>
 struct F64 {
     using LaneT = LaneF64;
 
@@ -190,16 +206,25 @@ struct F64 {
         rhs<Row, false>(L.row, u.tc, lb, L.y, L.k1);
         L.dt1 = 1.0;
         L.nrhs = 1;
+        L.nt = 0;
+        if (RECORD) tape_checkpoint(u, idx, 0, L.y);
         return 0;
     }
 
     static __device__ void finish(const Io& io, const Uni& u, const LaneT& L, int st) {
         write_out(io, u, L.idx, L.y, L.t, L.acc, L.rej, L.nrhs, st);
+        if (RECORD) {
+            double* tp = tape_of(u, L.idx);
+            const int nt = L.omega_mode ? L.nt : L.acc;
+            tp[0] = (double)nt;
+            tp[1] = (double)(L.acc - nt);
+        }
     }
 
     // One attempted step; 0 = continue, 1 = finished OK, < 0 = status.
     static __device__ __forceinline__ int step(const Uni& u, LaneT& L, bool any_w) {
         if (L.acc + L.rej >= u.max_steps) return PN_ST_MAX_STEPS;
+        if (RECORD && L.acc >= u.tape_cap) return PN_ST_TAPE_FULL;
         if (!L.omega_mode && u.rr_on && L.k1[0] <= 0.0) return PN_ST_OMEGADOT_NONPOSITIVE;
         if (L.omega_mode && L.dt1 <= 0.0) return PN_ST_OMEGADOT_NONPOSITIVE;
 
@@ -296,6 +321,7 @@ struct F64 {
                 // the candidate passes omega_f: discard it and finish the stretch
                 // with omega as the independent variable
                 L.omega_mode = true;
+                L.nt = L.acc;
                 const double s = 1.0 / L.k1[0];
 #pragma unroll
                 for (int c = 1; c < 10; ++c) L.k1[c] *= s;
@@ -309,6 +335,10 @@ struct F64 {
 #pragma unroll
             for (int c = 0; c < 10; ++c) { L.y[c] = Y[c]; L.k1[c] = k7[c]; }
             L.dt1 = dt7;
+            if (RECORD) {
+                tape_of(u, L.idx)[2 + L.acc] = h;
+                if ((L.acc + 1) % u.ckpt_every == 0) tape_checkpoint(u, L.idx, (L.acc + 1) / u.ckpt_every, L.y);
+            }
             L.acc += 1;
             if (!L.omega_mode && !u.tend && L.y[0] == u.omega_f) last = true;
             if (last) {
@@ -585,10 +615,10 @@ __device__ __forceinline__ void static_loop(const Io& io, const Uni& u, int64_t 
     }
 }
 
-template <int BLOCK>
+template <int BLOCK, bool RECORD>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(PN_WPE_F64)))
 void integrate_persistent_f64(Io io, Uni u, unsigned long long* counter) {
-    persistent_loop<F64>(io, u, counter);
+    persistent_loop<F64<RECORD>>(io, u, counter);
 }
 
 template <int BLOCK>
@@ -597,16 +627,283 @@ void integrate_persistent_f32s(Io io, Uni u, unsigned long long* counter) {
     persistent_loop<F32Split>(io, u, counter);
 }
 
-template <int BLOCK>
+template <int BLOCK, bool RECORD>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(PN_WPE_F64)))
 void integrate_static_f64(Io io, Uni u) {
-    static_loop<F64>(io, u, (int64_t)blockIdx.x * BLOCK + threadIdx.x);
+    static_loop<F64<RECORD>>(io, u, (int64_t)blockIdx.x * BLOCK + threadIdx.x);
 }
 
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(PN_WPE_F32)))
 void integrate_static_f32s(Io io, Uni u) {
     static_loop<F32Split>(io, u, (int64_t)blockIdx.x * BLOCK + threadIdx.x);
+}
+
+// ===========================================================================
+// Discrete adjoint (reverse mode of the replayed FP64 Dormand-Prince map)
+// ===========================================================================
+//
+// The forward map, with the recorded step sizes frozen: n_t time steps
+// y <- Phi_f(y, h_k), then n_w steps in omega, z = (t, y) <- Phi_g(z, D_j),
+// g = (1/f_0, 1, f_1/f_0, ..., f_9/f_0), the last D = omega_f - omega.  The
+// backward pass walks the checkpoint segments from the last one: it replays
+// K steps forward from the checkpoint (states into the workspace), then
+// runs the RK adjoint recurrence through them in reverse:
+//   Lambda_i = h (b_i lambda_{n+1} + sum_{j>i} a_ji mu_j),  mu_i = J(Y_i)^T Lambda_i,
+//   lambda_n = lambda_{n+1} + sum_i mu_i,
+// plus dL/dD * dD/domega_n = -dL/dD for the last omega-step.
+
+struct AdjUni {
+    double omega_f;
+    TermConsts tc;
+    int64_t n, ld;
+    int terms, theta_literal;
+    const double* tape;
+    int64_t tape_stride;
+    int tape_cap, ckpt_every;
+};
+
+struct AdjIo {
+    const double* __restrict__ m;
+    const int32_t* __restrict__ status;
+    const double* __restrict__ gy;      // [10][ld]
+    const double* __restrict__ gt;      // [ld] or null
+    double* __restrict__ g_m;           // [2][ld]
+    double* __restrict__ g_S0;          // [6][ld]
+    double* __restrict__ g_L0;          // [3][ld]
+    double* __restrict__ g_w0;          // [ld]
+    double* __restrict__ ws;            // [n][K][10]
+    const int32_t* __restrict__ order;  // [n] or null
+};
+
+// the stage derivative: f (time mode) or g (omega mode, dt/domega in *gt)
+__device__ __forceinline__ void stage_deriv(const Row& R, const TermConsts& tc, const double* Y, double* k,
+                                            bool om) {
+    LogBase lb;
+    rhs<Row, false>(R, tc, lb, Y, k);
+    if (om) {
+        const double s = 1.0 / k[0];
+#pragma unroll
+        for (int c = 1; c < 10; ++c) k[c] *= s;
+        k[0] = 1.0;
+    }
+}
+
+// one replayed step (no error control): y <- y + h sum b_i k_i
+__device__ __forceinline__ void replay_step(const Row& R, const TermConsts& tc, double* y, double h, bool om) {
+    double k1[10], k2[10], k3[10], k4[10], k5[10], k6[10], Y[10];
+    stage_deriv(R, tc, y, k1, om);
+#pragma unroll
+    for (int c = 0; c < 10; ++c) Y[c] = __builtin_fma(h * A21, k1[c], y[c]);
+    stage_deriv(R, tc, Y, k2, om);
+#pragma unroll
+    for (int c = 0; c < 10; ++c) Y[c] = __builtin_fma(h * A32, k2[c], __builtin_fma(h * A31, k1[c], y[c]));
+    stage_deriv(R, tc, Y, k3, om);
+#pragma unroll
+    for (int c = 0; c < 10; ++c)
+        Y[c] = __builtin_fma(h * A43, k3[c], __builtin_fma(h * A42, k2[c], __builtin_fma(h * A41, k1[c], y[c])));
+    stage_deriv(R, tc, Y, k4, om);
+#pragma unroll
+    for (int c = 0; c < 10; ++c)
+        Y[c] = __builtin_fma(h * A54, k4[c], __builtin_fma(h * A53, k3[c],
+               __builtin_fma(h * A52, k2[c], __builtin_fma(h * A51, k1[c], y[c]))));
+    stage_deriv(R, tc, Y, k5, om);
+#pragma unroll
+    for (int c = 0; c < 10; ++c)
+        Y[c] = __builtin_fma(h * A65, k5[c], __builtin_fma(h * A64, k4[c], __builtin_fma(h * A63, k3[c],
+               __builtin_fma(h * A62, k2[c], __builtin_fma(h * A61, k1[c], y[c])))));
+    stage_deriv(R, tc, Y, k6, om);
+#pragma unroll
+    for (int c = 0; c < 10; ++c)
+        y[c] = __builtin_fma(h * B6, k6[c], __builtin_fma(h * B5, k5[c], __builtin_fma(h * B4, k4[c],
+               __builtin_fma(h * B3, k3[c], __builtin_fma(h * B1, k1[c], y[c])))));
+}
+
+// Reverse of one step from state y (before the step).  lam (10) and the row
+// adjoint are updated in place; lt is dL/dt (constant along the path).
+// `last` marks the last omega-step, whose size depends on y[0].
+__device__ __forceinline__ void reverse_step(const Row& R, const TermConsts& tc, const double* y, double h, bool om,
+                                             bool last, double* lam, double lt, RowBar& rb) {
+    // forward stages (k1..k5 kept to rebuild the stage points in reverse)
+    double k1[10], k2[10], k3[10], k4[10], k5[10], Y[10];
+    stage_deriv(R, tc, y, k1, om);
+#pragma unroll
+    for (int c = 0; c < 10; ++c) Y[c] = __builtin_fma(h * A21, k1[c], y[c]);
+    stage_deriv(R, tc, Y, k2, om);
+#pragma unroll
+    for (int c = 0; c < 10; ++c) Y[c] = __builtin_fma(h * A32, k2[c], __builtin_fma(h * A31, k1[c], y[c]));
+    stage_deriv(R, tc, Y, k3, om);
+#pragma unroll
+    for (int c = 0; c < 10; ++c)
+        Y[c] = __builtin_fma(h * A43, k3[c], __builtin_fma(h * A42, k2[c], __builtin_fma(h * A41, k1[c], y[c])));
+    stage_deriv(R, tc, Y, k4, om);
+#pragma unroll
+    for (int c = 0; c < 10; ++c)
+        Y[c] = __builtin_fma(h * A54, k4[c], __builtin_fma(h * A53, k3[c],
+               __builtin_fma(h * A52, k2[c], __builtin_fma(h * A51, k1[c], y[c]))));
+    stage_deriv(R, tc, Y, k5, om);
+
+    // reverse: stage i = 6 .. 1, mu_j kept for j > i
+    double mu6[10], mu5[10], mu4[10], mu3[10], mu2[10], Lb[10];
+    double lnew[10];
+#pragma unroll
+    for (int c = 0; c < 10; ++c) lnew[c] = lam[c];
+    double dh = 0.0;     // dL/dh (last omega-step only)
+
+    auto stage = [&](const double* Yi, const double* Lam_over_h, double bi, double* mu) {
+        // Lam_over_h = b_i lam + sum_{j>i} a_ji mu_j ; Lambda_i = h * that
+        double Lam[10], gi[10];
+#pragma unroll
+        for (int c = 0; c < 10; ++c) { Lam[c] = h * Lam_over_h[c]; mu[c] = 0.0; }
+        rhs_vjp(R, tc, Yi, Lam, lt * h * bi, om, mu, rb);
+        if (last) {
+            // dL/dh = sum_i k_i . (b_i lam + sum_{j>i} a_ji mu_j) + lt sum_i b_i dt/domega(Y_i)
+            stage_deriv(R, tc, Yi, gi, om);
+            double dot = 0.0;
+#pragma unroll
+            for (int c = 0; c < 10; ++c) dot = __builtin_fma(gi[c], Lam_over_h[c], dot);
+            LogBase lb;
+            double f[10];
+            rhs<Row, false>(R, tc, lb, Yi, f);
+            dh += dot + lt * bi / f[0];
+        }
+#pragma unroll
+        for (int c = 0; c < 10; ++c) lnew[c] += mu[c];
+    };
+
+    // stage 6
+#pragma unroll
+    for (int c = 0; c < 10; ++c)
+        Y[c] = __builtin_fma(h * A65, k5[c], __builtin_fma(h * A64, k4[c], __builtin_fma(h * A63, k3[c],
+               __builtin_fma(h * A62, k2[c], __builtin_fma(h * A61, k1[c], y[c])))));
+#pragma unroll
+    for (int c = 0; c < 10; ++c) Lb[c] = B6 * lam[c];
+    stage(Y, Lb, B6, mu6);
+    // stage 5
+#pragma unroll
+    for (int c = 0; c < 10; ++c)
+        Y[c] = __builtin_fma(h * A54, k4[c], __builtin_fma(h * A53, k3[c],
+               __builtin_fma(h * A52, k2[c], __builtin_fma(h * A51, k1[c], y[c]))));
+#pragma unroll
+    for (int c = 0; c < 10; ++c) Lb[c] = __builtin_fma(A65, mu6[c], B5 * lam[c]);
+    stage(Y, Lb, B5, mu5);
+    // stage 4
+#pragma unroll
+    for (int c = 0; c < 10; ++c)
+        Y[c] = __builtin_fma(h * A43, k3[c], __builtin_fma(h * A42, k2[c], __builtin_fma(h * A41, k1[c], y[c])));
+#pragma unroll
+    for (int c = 0; c < 10; ++c) Lb[c] = __builtin_fma(A64, mu6[c], __builtin_fma(A54, mu5[c], B4 * lam[c]));
+    stage(Y, Lb, B4, mu4);
+    // stage 3
+#pragma unroll
+    for (int c = 0; c < 10; ++c) Y[c] = __builtin_fma(h * A32, k2[c], __builtin_fma(h * A31, k1[c], y[c]));
+#pragma unroll
+    for (int c = 0; c < 10; ++c)
+        Lb[c] = __builtin_fma(A63, mu6[c], __builtin_fma(A53, mu5[c], __builtin_fma(A43, mu4[c], B3 * lam[c])));
+    stage(Y, Lb, B3, mu3);
+    // stage 2 (b2 = 0)
+#pragma unroll
+    for (int c = 0; c < 10; ++c) Y[c] = __builtin_fma(h * A21, k1[c], y[c]);
+#pragma unroll
+    for (int c = 0; c < 10; ++c)
+        Lb[c] = __builtin_fma(A62, mu6[c], __builtin_fma(A52, mu5[c], __builtin_fma(A42, mu4[c], A32 * mu3[c])));
+    stage(Y, Lb, 0.0, mu2);
+    // stage 1 (Y_1 = y)
+#pragma unroll
+    for (int c = 0; c < 10; ++c)
+        Lb[c] = __builtin_fma(A61, mu6[c], __builtin_fma(A51, mu5[c], __builtin_fma(A41, mu4[c],
+                __builtin_fma(A31, mu3[c], __builtin_fma(A21, mu2[c], B1 * lam[c])))));
+    double mu1[10];
+    stage(y, Lb, B1, mu1);
+
+#pragma unroll
+    for (int c = 0; c < 10; ++c) lam[c] = lnew[c];
+    if (last) lam[0] -= dh;      // D = omega_f - omega_n
+}
+
+__device__ void adjoint_one(const AdjIo& io, const AdjUni& u, int64_t idx) {
+    const int64_t ld = u.ld;
+    const int st = io.status[idx];
+    const double* tp = u.tape + idx * u.tape_stride;
+    double lam[10];
+#pragma unroll
+    for (int c = 0; c < 10; ++c) lam[c] = io.gy[c * ld + idx];
+    if (st == PN_ST_DONE_AT_START || st != PN_ST_OK) {
+        // done at start: the output is the input; failures: no gradient
+        const double fill = (st == PN_ST_DONE_AT_START) ? 1.0 : __builtin_nan("");
+        io.g_m[idx] = st == PN_ST_DONE_AT_START ? 0.0 : fill;
+        io.g_m[ld + idx] = st == PN_ST_DONE_AT_START ? 0.0 : fill;
+        io.g_w0[idx] = lam[0] * fill;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) io.g_S0[c * ld + idx] = lam[1 + c] * fill;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) io.g_L0[c * ld + idx] = lam[7 + c] * fill;
+        return;
+    }
+    const double m1 = io.m[idx], m2 = io.m[ld + idx];
+    Row R;
+    make_row(R, m1, m2, u.terms, u.theta_literal);
+    RowBar rb;
+#pragma unroll
+    for (int i = 0; i < NROW; ++i) rb.v[i] = 0.0;
+    const double lt = io.gt ? io.gt[idx] : 0.0;
+    const int nt = (int)tp[0];
+    const int N = nt + (int)tp[1];
+    const int K = u.ckpt_every;
+    const double* hs = tp + 2;
+    const double* ck = tp + 2 + u.tape_cap;
+    double* ws = io.ws + idx * (int64_t)K * 10;
+    const int nseg = (N + K - 1) / K;
+    for (int sg = nseg - 1; sg >= 0; --sg) {
+        const int k0 = sg * K;
+        const int k1 = (k0 + K < N) ? k0 + K : N;
+        double y[10];
+#pragma unroll
+        for (int c = 0; c < 10; ++c) y[c] = ck[(int64_t)sg * 10 + c];
+        for (int k = k0; k < k1; ++k) {
+#pragma unroll
+            for (int c = 0; c < 10; ++c) ws[(k - k0) * 10 + c] = y[c];
+            if (k + 1 < k1) {    // the state after the segment's last step is not needed
+                const bool om = k >= nt;
+                const double h = (om && k == N - 1) ? u.omega_f - y[0] : hs[k];
+                replay_step(R, u.tc, y, h, om);
+            }
+        }
+        for (int k = k1 - 1; k >= k0; --k) {
+#pragma unroll
+            for (int c = 0; c < 10; ++c) y[c] = ws[(k - k0) * 10 + c];
+            const bool om = k >= nt;
+            const bool last = om && k == N - 1;
+            const double h = last ? u.omega_f - y[0] : hs[k];
+            reverse_step(R, u.tc, y, h, om, last, lam, lt, rb);
+        }
+    }
+    // chain the row adjoint to the masses
+    double gm[2];
+#pragma unroll
+    for (int dir = 0; dir < 2; ++dir) {
+        RowDual rd;
+        make_row_dual(rd, Dl(m1, dir == 0 ? 1.0 : 0.0), Dl(m2, dir == 1 ? 1.0 : 0.0), u.terms, u.theta_literal);
+        double g = 0.0;
+#pragma unroll
+        for (int i = 0; i < NROW; ++i) g = __builtin_fma(rb.v[i], rd.v[i].d, g);
+        gm[dir] = g;
+    }
+    io.g_m[idx] = gm[0];
+    io.g_m[ld + idx] = gm[1];
+    io.g_w0[idx] = lam[0];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) io.g_S0[c * ld + idx] = lam[1 + c];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) io.g_L0[c * ld + idx] = lam[7 + c];
+}
+
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void adjoint_kernel(AdjIo io, AdjUni u) {
+    const int64_t j = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (j >= u.n) return;
+    const int64_t idx = io.order ? (int64_t)io.order[j] : j;
+    adjoint_one(io, u, idx);
 }
 
 __global__ void reset_counter(unsigned long long* c) { *c = 0ull; }
@@ -696,7 +993,8 @@ hipError_t launch_forward(const Io& io, const Uni& u, int precision, int schedul
     if (schedule == PN_SCHED_STATIC) {
         const int64_t grid = (u.n + BLOCK - 1) / BLOCK;
         if (f32) hipLaunchKernelGGL(integrate_static_f32s<BLOCK>, dim3((unsigned)grid), dim3(BLOCK), 0, s, io, u);
-        else hipLaunchKernelGGL(integrate_static_f64<BLOCK>, dim3((unsigned)grid), dim3(BLOCK), 0, s, io, u);
+        else if (u.tape) hipLaunchKernelGGL((integrate_static_f64<BLOCK, true>), dim3((unsigned)grid), dim3(BLOCK), 0, s, io, u);
+        else hipLaunchKernelGGL((integrate_static_f64<BLOCK, false>), dim3((unsigned)grid), dim3(BLOCK), 0, s, io, u);
         return hipGetLastError();
     }
     hipLaunchKernelGGL(reset_counter, dim3(1), dim3(1), 0, s, counter);
@@ -708,8 +1006,10 @@ hipError_t launch_forward(const Io& io, const Uni& u, int precision, int schedul
     const int64_t grid = (waves * 64 + BLOCK - 1) / BLOCK;
     if (f32)
         hipLaunchKernelGGL(integrate_persistent_f32s<BLOCK>, dim3((unsigned)grid), dim3(BLOCK), 0, s, io, u, counter);
+    else if (u.tape)
+        hipLaunchKernelGGL((integrate_persistent_f64<BLOCK, true>), dim3((unsigned)grid), dim3(BLOCK), 0, s, io, u, counter);
     else
-        hipLaunchKernelGGL(integrate_persistent_f64<BLOCK>, dim3((unsigned)grid), dim3(BLOCK), 0, s, io, u, counter);
+        hipLaunchKernelGGL((integrate_persistent_f64<BLOCK, false>), dim3((unsigned)grid), dim3(BLOCK), 0, s, io, u, counter);
     return hipGetLastError();
 }
 
@@ -732,10 +1032,10 @@ const char* pn_strerror(int code) {
 
 const char* pn_version(void) { return "pn-gfx950 0.2"; }
 
-int pn_integrate(int64_t n, int64_t ld, const double* m, const double* S0, const double* L0,
-                 const double* omega0, double omega_f, double tol, const pn_opts* opt,
-                 double* y_final, double* t_final, int32_t* steps, int32_t* status, double* dots,
-                 void* stream) {
+static int integrate_impl(int64_t n, int64_t ld, const double* m, const double* S0, const double* L0,
+                          const double* omega0, double omega_f, double tol, const pn_opts* opt,
+                          double* y_final, double* t_final, int32_t* steps, int32_t* status, double* dots,
+                          double* tape, int64_t cap_steps, int32_t ckpt_every, void* stream) {
     pn_opts o;
     std::memset(&o, 0, sizeof(o));
     if (opt) o = *opt;
@@ -760,6 +1060,10 @@ int pn_integrate(int64_t n, int64_t ld, const double* m, const double* S0, const
     if (refill < 1 || refill > 64) return PN_EINVAL;
     if (o.terms < 0 || o.terms > PN_TERM_ALL) return PN_EINVAL;
     if (o.theta_literal != 0 && o.theta_literal != 1) return PN_EINVAL;
+    if (tape) {
+        if (o.precision != PN_PREC_FP64 || tend) return PN_EINVAL;
+        if (cap_steps < 1 || cap_steps > (1 << 28) || ckpt_every < 1 || ckpt_every > 4096) return PN_EINVAL;
+    }
     if (n == 0) return PN_OK;
 
     DevCtx* ctx = nullptr;
@@ -784,6 +1088,10 @@ int pn_integrate(int64_t n, int64_t ld, const double* m, const double* S0, const
     u.tend = tend;
     u.refill_min = refill;
     u.rr_on = (u.terms & PN_TERM_RR) != 0;
+    u.tape = tape;
+    u.tape_stride = tape ? (int64_t)pn_tape_stride(cap_steps, ckpt_every) : 0;
+    u.tape_cap = (int)cap_steps;
+    u.ckpt_every = ckpt_every > 0 ? ckpt_every : 1;
 
     Io io;
     io.m = m; io.S0 = S0; io.L0 = L0; io.w0 = omega0;
@@ -799,6 +1107,71 @@ int pn_integrate(int64_t n, int64_t ld, const double* m, const double* S0, const
         default: e = launch_forward<256>(io, u, o.precision, o.schedule, wps, ctx->cus, counter, s); break;
     }
     return e == hipSuccess ? PN_OK : PN_EHIP;
+}
+
+int pn_integrate(int64_t n, int64_t ld, const double* m, const double* S0, const double* L0,
+                 const double* omega0, double omega_f, double tol, const pn_opts* opt,
+                 double* y_final, double* t_final, int32_t* steps, int32_t* status, double* dots,
+                 void* stream) {
+    return integrate_impl(n, ld, m, S0, L0, omega0, omega_f, tol, opt, y_final, t_final, steps, status, dots,
+                          nullptr, 0, 0, stream);
+}
+
+size_t pn_tape_stride(int64_t cap_steps, int32_t ckpt_every) {
+    if (cap_steps < 1 || ckpt_every < 1) return 0;
+    return (size_t)(2 + cap_steps + 10 * (cap_steps / ckpt_every + 1));
+}
+
+int pn_integrate_record(int64_t n, int64_t ld, const double* m, const double* S0, const double* L0,
+                        const double* omega0, double omega_f, double tol, const pn_opts* opt,
+                        double* y_final, double* t_final, int32_t* steps, int32_t* status, double* dots,
+                        double* tape, int64_t cap_steps, int32_t ckpt_every, void* stream) {
+    if (n > 0 && !tape) return PN_EINVAL;
+    return integrate_impl(n, ld, m, S0, L0, omega0, omega_f, tol, opt, y_final, t_final, steps, status, dots,
+                          tape, cap_steps, ckpt_every, stream);
+}
+
+size_t pn_adjoint_workspace_bytes(int64_t n, int32_t ckpt_every) {
+    if (n < 0 || ckpt_every < 1) return 0;
+    return (size_t)n * (size_t)ckpt_every * 10 * sizeof(double);
+}
+
+int pn_integrate_adjoint(int64_t n, int64_t ld, const double* m, double omega_f, const pn_opts* opt,
+                         const double* tape, int64_t cap_steps, int32_t ckpt_every, const int32_t* status,
+                         const double* gy_final, const double* gt_final, double* g_m, double* g_S0,
+                         double* g_L0, double* g_omega0, double* workspace, size_t ws_bytes,
+                         const int32_t* order, void* stream) {
+    if (n < 0 || ld < n) return PN_EINVAL;
+    if (cap_steps < 1 || cap_steps > (1 << 28) || ckpt_every < 1 || ckpt_every > 4096) return PN_EINVAL;
+    if (n > 0 && (!m || !tape || !status || !gy_final || !g_m || !g_S0 || !g_L0 || !g_omega0 || !workspace))
+        return PN_EINVAL;
+    if (!(omega_f > 0.0 && omega_f < 1e300)) return PN_EINVAL;
+    if (ws_bytes < pn_adjoint_workspace_bytes(n, ckpt_every)) return PN_EINVAL;
+    const int terms = (opt && opt->terms > 0) ? opt->terms : PN_TERM_ALL;
+    const int lit = opt ? opt->theta_literal : 0;
+    if ((opt && opt->terms > PN_TERM_ALL) || (lit != 0 && lit != 1)) return PN_EINVAL;
+    if (opt && (opt->precision != PN_PREC_FP64 || opt->t_end > 0.0 || opt->h_fixed > 0.0)) return PN_EINVAL;
+    if (n == 0) return PN_OK;
+    DevCtx* ctx = nullptr;
+    int rc = get_ctx(&ctx);
+    if (rc != PN_OK) return rc;
+    AdjUni u;
+    u.omega_f = omega_f;
+    u.tc = term_consts(terms);
+    u.n = n;
+    u.ld = ld;
+    u.terms = terms;
+    u.theta_literal = lit;
+    u.tape = tape;
+    u.tape_stride = (int64_t)pn_tape_stride(cap_steps, ckpt_every);
+    u.tape_cap = (int)cap_steps;
+    u.ckpt_every = ckpt_every;
+    AdjIo io;
+    io.m = m; io.status = status; io.gy = gy_final; io.gt = gt_final;
+    io.g_m = g_m; io.g_S0 = g_S0; io.g_L0 = g_L0; io.g_w0 = g_omega0; io.ws = workspace; io.order = order;
+    const int64_t grid = (n + 127) / 128;
+    hipLaunchKernelGGL(adjoint_kernel<128>, dim3((unsigned)grid), dim3(128), 0, (hipStream_t)stream, io, u);
+    return hipGetLastError() == hipSuccess ? PN_OK : PN_EHIP;
 }
 
 int pn_rhs(int64_t n, int64_t ld, const double* m, const double* y, double* dydt, const pn_opts* opt,

@@ -1,0 +1,191 @@
+"""The discrete adjoint (pn_integrate_adjoint) against the oracle.
+
+The adjoint differentiates the Dormand-Prince map with the accepted step
+sizes frozen.  The GPU's own recorded step sequence is replayed by the
+oracle, so both sides differentiate the same map:
+  * the oracle's forward-mode tangent (dual numbers) along random directions
+    must satisfy <grad, direction> = <gy, dy_final> + gt dt_final
+    (the adjoint/tangent identity), to rounding;
+  * central differences of the oracle's replay (h = 1e-6) agree to ~1e-6;
+  * the checkpoint spacing K does not change the result.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_0908_3889_amd import population as P
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_0908_3889_amd import _lib
+    _lib.load()
+    yield
+
+
+def _record(pop, K=16, cap=1024, **kw):
+    from paper_0908_3889_amd import api
+    d = api.to_device(pop)
+    rec = api.pn_integrate_record(d["m"], d["S"], d["L"], d["omega0"], pop["omega_f"], pop["tol"],
+                                  api.make_opts(**kw), cap_steps=cap, ckpt_every=K)
+    torch.cuda.synchronize()
+    return d, rec
+
+
+def _replay_of(rec):
+    tape = rec["tape"].cpu().numpy()
+    cap = rec["cap_steps"]
+    return {"h": np.ascontiguousarray(tape[:, 2:2 + cap]), "n_t": tape[:, 0].astype(np.int32),
+            "n_w": tape[:, 1].astype(np.int32)}
+
+
+def _adjoint(d, pop, rec, gy, gt, **kw):
+    from paper_0908_3889_amd import api
+    g = api.pn_integrate_adjoint(d["m"], pop["omega_f"], rec, torch.from_numpy(gy).cuda(),
+                                 None if gt is None else torch.from_numpy(gt).cuda(), api.make_opts(**kw))
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy() for k, v in g.items()}
+
+
+@pytest.mark.parametrize("workload,n", [("adjoint_64k", 300), ("q1to4_1M", 130), ("batching_4M", 65)])
+def test_adjoint_equals_oracle_tangent(workload, n):
+    pop = P.generate(workload, n)
+    d, rec = _record(pop, K=16, cap=4096)
+    st = rec["status"].cpu().numpy()
+    assert (st == 0).all()
+    replay = _replay_of(rec)
+    rng = np.random.default_rng(11)
+    gy = rng.normal(size=(10, n))
+    gt = rng.normal(size=n) * 1e-5
+    g = _adjoint(d, pop, rec, gy, gt)
+    dm = rng.normal(size=(2, n)) * 1e-2
+    dS = rng.normal(size=(6, n)) * 1e-2
+    dL = rng.normal(size=(3, n)) * 1e-2
+    dw = rng.normal(size=n) * 1e-5
+    tg = oracle.tangent(pop["m"], pop["S"], pop["L"], pop["omega0"], dm, dS, dL, dw, pop["omega_f"],
+                        pop["tol"], replay, nthreads=8)
+    assert (tg["status"] == 0).all()
+    # the oracle replays the GPU's step sequence to the GPU's final state
+    yg = rec["y"].cpu().numpy()
+    assert np.abs(tg["y"] - yg).max() < 1e-9
+    lhs = ((g["m"] * dm).sum(0) + (g["S0"] * dS).sum(0) + (g["L0"] * dL).sum(0) + g["omega0"] * dw)
+    rhs = (gy * tg["dy"]).sum(0) + gt * tg["dt"]
+    scale = np.abs(g["m"] * dm).sum(0) + np.abs(g["S0"] * dS).sum(0) + np.abs(g["L0"] * dL).sum(0) \
+        + np.abs(g["omega0"] * dw) + np.abs(gy * tg["dy"]).sum(0)
+    rel = np.abs(lhs - rhs) / scale
+    assert rel.max() < 1e-9, (rel.max(), int(rel.argmax()))
+
+
+def test_adjoint_against_central_differences_of_the_replay():
+    n = 12
+    pop = P.generate("adjoint_64k", n)
+    d, rec = _record(pop, K=16)
+    replay = _replay_of(rec)
+    rng = np.random.default_rng(5)
+    gy = rng.normal(size=(10, n))
+    gy[0] = 0.0
+    gt = rng.normal(size=n) * 1e-5
+    g = _adjoint(d, pop, rec, gy, gt)
+
+    def loss(m, S, L, w):
+        r = oracle.integrate(m, S, L, w, pop["omega_f"], pop["tol"], replay=replay, nthreads=8)
+        return (gy * r["y"]).sum(0) + gt * r["t"]
+
+    eps = 1e-6
+    base = dict(m=pop["m"], S=pop["S"], L=pop["L"], w=pop["omega0"])
+    checks = [("m", 2, g["m"]), ("S", 6, g["S0"]), ("L", 3, g["L0"]), ("w", 1, g["omega0"][None])]
+    for name, comps, grad in checks:
+        for c in range(comps):
+            plus = {k: v.copy() for k, v in base.items()}
+            minus = {k: v.copy() for k, v in base.items()}
+            if name == "w":
+                scale_in = pop["omega0"]
+                plus["w"] = plus["w"] + eps * scale_in
+                minus["w"] = minus["w"] - eps * scale_in
+            else:
+                scale_in = 1.0
+                plus[name][c] += eps
+                minus[name][c] -= eps
+            fd = (loss(**plus) - loss(**minus)) / (2 * eps)
+            ad = grad[c] * scale_in
+            assert np.abs(fd - ad).max() < 1e-6 * max(1.0, np.abs(ad).max()), (name, c, fd, ad)
+
+
+def test_checkpoint_spacing_does_not_change_the_gradient():
+    n = 200
+    pop = P.generate("adjoint_64k", n)
+    rng = np.random.default_rng(3)
+    gy = rng.normal(size=(10, n))
+    gt = rng.normal(size=n) * 1e-5
+    res = []
+    for K in (1, 16, 64, 256):
+        d, rec = _record(pop, K=K)
+        res.append(_adjoint(d, pop, rec, gy, gt))
+    for r in res[1:]:
+        for k in ("m", "S0", "L0", "omega0"):
+            np.testing.assert_allclose(r[k], res[0][k], rtol=1e-10, atol=1e-12 * np.abs(res[0][k]).max())
+
+
+def test_adjoint_status_handling():
+    n = 70
+    pop = P.generate("adjoint_64k", n)
+    pop["omega0"] = pop["omega0"].copy()
+    pop["omega0"][0] = 0.06                       # done at start: identity
+    d, rec = _record(pop, K=16)
+    st = rec["status"].cpu().numpy()
+    assert st[0] == 1 and (st[1:] == 0).all()
+    gy = np.random.default_rng(0).normal(size=(10, n))
+    g = _adjoint(d, pop, rec, gy, None)
+    np.testing.assert_array_equal(g["S0"][:, 0], gy[1:7, 0])
+    np.testing.assert_array_equal(g["L0"][:, 0], gy[7:, 0])
+    assert g["omega0"][0] == gy[0, 0] and (g["m"][:, 0] == 0).all()
+    # a too-small tape ends with TAPE_FULL and a NaN gradient
+    d, rec = _record(pop, K=16, cap=20)
+    st = rec["status"].cpu().numpy()
+    assert (st[1:] == -6).all()
+    g = _adjoint(d, pop, rec, gy, None)
+    assert np.isnan(g["S0"][:, 1:]).all()
+
+
+def test_autograd_function_loss_of_the_differentiation_workload():
+    """loss = sum_i S1(final).S2(final) + sum_i L_hat_z(final), differentiated
+    with respect to the initial spins and masses."""
+    from paper_0908_3889_amd import api
+    n = 256
+    pop = P.generate("adjoint_64k", n)
+    d = api.to_device(pop)
+    m = d["m"].clone().requires_grad_(True)
+    S = d["S"].clone().requires_grad_(True)
+    L = d["L"].clone().requires_grad_(True)
+    w = d["omega0"].clone().requires_grad_(True)
+    y, t, status, steps = api.PNIntegrate.apply(m, S, L, w, pop["omega_f"], pop["tol"], 16, 512)
+    loss = (y[1:4] * y[4:7]).sum() + y[9].sum()
+    loss.backward()
+    torch.cuda.synchronize()
+    assert (status == 0).all()
+    # the same through the explicit call, with gy = dloss/dy
+    yv = y.detach()
+    gy = torch.zeros_like(yv)
+    gy[1:4] = yv[4:7]
+    gy[4:7] = yv[1:4]
+    gy[9] = 1.0
+    rec = api.pn_integrate_record(d["m"], d["S"], d["L"], d["omega0"], pop["omega_f"], pop["tol"],
+                                  cap_steps=512, ckpt_every=16)
+    g = api.pn_integrate_adjoint(d["m"], pop["omega_f"], rec, gy)
+    torch.cuda.synchronize()
+    torch.testing.assert_close(S.grad, g["S0"], rtol=1e-12, atol=1e-14)
+    torch.testing.assert_close(m.grad, g["m"], rtol=1e-12, atol=1e-14)
+    # free (adaptive) finite differences agree only to the controller's O(tol) noise
+    i, eps = 3, 1e-6
+    Sp = d["S"].clone(); Sp[2, i] += eps
+    Sm = d["S"].clone(); Sm[2, i] -= eps
+    lp = api.pn_integrate(d["m"], Sp, d["L"], d["omega0"], pop["omega_f"], pop["tol"])["y"]
+    lm = api.pn_integrate(d["m"], Sm, d["L"], d["omega0"], pop["omega_f"], pop["tol"])["y"]
+    f = lambda yy: float(((yy[1:4] * yy[4:7]).sum(0) + yy[9])[i])
+    fd = (f(lp) - f(lm)) / (2 * eps)
+    assert abs(fd - float(S.grad[2, i])) < 1e-2 * max(1.0, abs(fd))
