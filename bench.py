@@ -74,6 +74,94 @@ def cpu_baseline(pop: dict, budget_s: float = 12.0) -> dict:
             "rhs_evals_per_s": float(r["steps"][2].sum()) / dt}
 
 
+PROFILES = os.path.join(ROOT, "profiles")
+COPY_CAL_BYTES = 512 << 20
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` on `workload`, from the committed
+    counter summary profiles/hbm_<kernel>_<workload>.txt (FETCH_SIZE and
+    WRITE_SIZE, each scaled by what the counter reads for a plain copy of known
+    size).  None when there is no such summary or the device sources have
+    changed since the counters were taken."""
+    from paper_0908_3889_amd import build
+    path = os.path.join(PROFILES, f"hbm_{kernel}_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if ":" in line and not line.startswith((" ", "#")):
+            k, v = line.split(":", 1)
+            fields[k.strip()] = v.strip()
+    if fields.get("source_digest") != build.source_digest():
+        return None
+    try:
+        return float(fields["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def calibrate_copy() -> int:
+    """Three device-to-device copies of COPY_CAL_BYTES each (the reference
+    kernel for scaling the FETCH_SIZE / WRITE_SIZE counters)."""
+    import torch
+    a = torch.ones(COPY_CAL_BYTES // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": COPY_CAL_BYTES, "copies": 3}), flush=True)
+    return 0
+
+
+def _time(fn, steps, warmup, stream):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    for a, b in ev:
+        a.record(stream)
+        fn()
+        b.record(stream)
+    torch.cuda.synchronize()
+    return float(np.mean([a.elapsed_time(b) for a, b in ev]))
+
+
+def bench_adjoint(args, api, pop, d, w, step, stream) -> int:
+    """Cost of the recorded forward and of the discrete adjoint relative to
+    the plain forward, per checkpoint spacing K (one JSON line)."""
+    import torch
+    t_fwd = _time(step, args.steps, args.warmup, stream)
+    out = {"metric": "adjoint/fwd cost", "workload": w.name, "n": pop["n"], "tol": w.tol,
+           "loss": "sum S1.S2 + sum L_hat_z (final)", "fwd_ms": t_fwd, "per_K": {}}
+    for K in [int(k) for k in args.adjoint.split(",")]:
+        box = {}
+
+        def rec():
+            box["rec"] = api.pn_integrate_record(d["m"], d["S"], d["L"], d["omega0"], pop["omega_f"],
+                                                 pop["tol"], cap_steps=1024, ckpt_every=K, stream=stream)
+        t_rec = _time(rec, args.steps, args.warmup, stream)
+        r = box["rec"]
+        y = r["y"]
+        gy = torch.zeros_like(y)
+        gy[1:4] = y[4:7]
+        gy[4:7] = y[1:4]
+        gy[9] = 1.0
+        order = torch.argsort(r["steps"][0], descending=True).to(torch.int32)
+
+        def adj():
+            box["g"] = api.pn_integrate_adjoint(d["m"], pop["omega_f"], r, gy, order=order, stream=stream)
+        t_adj = _time(adj, args.steps, args.warmup, stream)
+        ok = int((r["status"] == 0).sum())
+        out["per_K"][K] = {"record_ms": t_rec, "adjoint_ms": t_adj, "r_ckpt": t_rec / t_fwd,
+                           "r_bwd": t_adj / t_fwd, "r_total": (t_rec + t_adj) / t_fwd, "ok": ok,
+                           "grad_finite": bool(torch.isfinite(box["g"]["S0"]).all())}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -86,6 +174,11 @@ def main() -> int:
     ap.add_argument("--refill-min", type=int, default=0)
     ap.add_argument("--precision", default=None, choices=["fp64", "fp32split"],
                     help="default: the workload's own precision")
+    ap.add_argument("--adjoint", default=None,
+                    help="comma-separated checkpoint spacings K: time the recorded forward and the "
+                         "discrete adjoint of loss = sum S1.S2 + sum L_hat_z against the plain forward")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run three plain device copies of 512 MiB (counter calibration)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     args = ap.parse_args()
@@ -97,6 +190,9 @@ def main() -> int:
         return 2
 
     import torch
+
+    if args.calibrate_copy:
+        return calibrate_copy()
 
     from paper_0908_3889_amd import api, population
 
@@ -113,6 +209,9 @@ def main() -> int:
     def step():
         api.pn_integrate(d["m"], d["S"], d["L"], d["omega0"], pop["omega_f"], pop["tol"], opts,
                          out=out, stream=stream)
+
+    if args.adjoint:
+        return bench_adjoint(args, api, pop, d, w, step, stream)
 
     for _ in range(args.warmup):
         step()
@@ -141,6 +240,8 @@ def main() -> int:
     peak = FP64_VECTOR_PEAK_TFLOPS if precision == "fp64" else FP32_VECTOR_PEAK_TFLOPS
     n = pop["n"]
     value = n * args.steps / wall
+    kernel = f"integrate_{args.schedule}_{'f64' if precision == 'fp64' else 'f32s'}"
+    traffic = measured_traffic(kernel, w.name)
     res = {
         "metric": METRIC,
         "value": value,
@@ -159,7 +260,8 @@ def main() -> int:
                    "precision": precision, "schedule": args.schedule, "parallelism": "single GPU"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak,
                      "unit": "TFLOP/s", "frac": achieved / peak,
-                     "traffic": None},
+                     "traffic": traffic},
+        "kernel": kernel,
         "kernel_ms": avg_ms,
         "rhs_evals_per_s": float(steps[2].astype(np.int64).sum()) / (avg_ms * 1e-3),
         "attempted_steps": int(((steps[2].astype(np.int64) - 1) // 6).sum()),

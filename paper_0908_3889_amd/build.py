@@ -9,6 +9,7 @@ build_resource_usage.txt beside the library.
 """
 from __future__ import annotations
 
+import hashlib
 import os
 import shutil
 import subprocess
@@ -46,6 +47,19 @@ def build(verbose: bool = False) -> str:
         raise RuntimeError("hipcc failed building libpn.so")
     os.replace(LIB + ".tmp", LIB)
     return LIB
+
+
+def source_digest() -> str:
+    """sha256 over the device sources and the C header (file names and bytes),
+    identifying the kernels that a stored counter reading was taken on."""
+    h = hashlib.sha256()
+    files = sorted(f for f in os.listdir(CSRC) if f.endswith((".hip", ".hpp")))
+    for f in files + ["../../include/pn.h"]:
+        path = os.path.normpath(os.path.join(CSRC, f))
+        h.update(os.path.basename(path).encode())
+        with open(path, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
 
 
 def resource_usage() -> dict:

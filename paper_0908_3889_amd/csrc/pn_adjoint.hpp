@@ -22,15 +22,23 @@ struct RowBar {
 // (the weight of dt/domega) are first turned into fbar:
 //   s = 1/f_0,  sbar = gtbar + sum_{c>=1} gbar_c f_c,
 //   fbar_c = gbar_c s (c >= 1),  fbar_0 = -s^2 sbar.
-__device__ __forceinline__ void rhs_vjp(const Row& r, const TermConsts& tc, const double* __restrict__ y,
-                                        const double* __restrict__ gbar_in, double gtbar, bool omega_mode,
-                                        double* __restrict__ ybar, RowBar& rb) {
+//
+// gscale multiplies gbar_in (the step size of the RK adjoint recurrence).
+__device__ __forceinline__ void rhs_vjp(const Row& r, const TermConsts& tc, const LogBase& lb,
+                                        const double* __restrict__ y,
+                                        const double* __restrict__ gbar_in, double gscale, double gtbar,
+                                        bool omega_mode, double* __restrict__ ybar, RowBar& rb) {
     // ---------------- primal ----------------
     const double w = y[0];
     const double M = r[R_M];
     const double v = M * w;
     const double x = cbrt_real(v);
-    const double lnv = log_pos(__builtin_fabs(v));
+    double lnv;
+    {
+        const double uu = (w - lb.w) * lb.iw;
+        if (__builtin_fabs(uu) <= 0.125) lnv = lb.lnv + log1p_small(uu);
+        else lnv = log_pos(__builtin_fabs(v));
+    }
     const double x2 = x * x;
     const double L0 = y[7], L1 = y[8], L2 = y[9];
     const double a0 = y[1], a1 = y[2], a2 = y[3];
@@ -57,23 +65,23 @@ __device__ __forceinline__ void rhs_vjp(const Row& r, const TermConsts& tc, cons
     const double A1 = __builtin_fma(r[R_G1], x2, -3.0 * sv * LS2);
     const double A2 = __builtin_fma(r[R_G2], x2, -3.0 * sv * LS1);
     const double al1 = p * A1, al2 = p * A2, be = p * sv;
-    const double u0 = __builtin_fma(L1, a2, -L2 * a1), u1 = __builtin_fma(L2, a0, -L0 * a2),
-                 u2 = __builtin_fma(L0, a1, -L1 * a0);
-    const double w0 = __builtin_fma(L1, b2, -L2 * b1), w1 = __builtin_fma(L2, b0, -L0 * b2),
-                 w2 = __builtin_fma(L0, b1, -L1 * b0);
-    const double C0 = __builtin_fma(a1, b2, -a2 * b1), C1 = __builtin_fma(a2, b0, -a0 * b2),
-                 C2 = __builtin_fma(a0, b1, -a1 * b0);
-    const double dS1_0 = __builtin_fma(al1, u0, -be * C0), dS1_1 = __builtin_fma(al1, u1, -be * C1),
-                 dS1_2 = __builtin_fma(al1, u2, -be * C2);
-    const double dS2_0 = __builtin_fma(al2, w0, be * C0), dS2_1 = __builtin_fma(al2, w1, be * C1),
-                 dS2_2 = __builtin_fma(al2, w2, be * C2);
     const double q = -r[R_LAM] * x;
 
     // ---------------- seed fbar ----------------
     double fb[10];
     if (omega_mode) {
+        const double u0 = __builtin_fma(L1, a2, -L2 * a1), u1 = __builtin_fma(L2, a0, -L0 * a2),
+                     u2 = __builtin_fma(L0, a1, -L1 * a0);
+        const double w0 = __builtin_fma(L1, b2, -L2 * b1), w1 = __builtin_fma(L2, b0, -L0 * b2),
+                     w2 = __builtin_fma(L0, b1, -L1 * b0);
+        const double C0 = __builtin_fma(a1, b2, -a2 * b1), C1 = __builtin_fma(a2, b0, -a0 * b2),
+                     C2 = __builtin_fma(a0, b1, -a1 * b0);
+        const double dS1_0 = __builtin_fma(al1, u0, -be * C0), dS1_1 = __builtin_fma(al1, u1, -be * C1),
+                     dS1_2 = __builtin_fma(al1, u2, -be * C2);
+        const double dS2_0 = __builtin_fma(al2, w0, be * C0), dS2_1 = __builtin_fma(al2, w1, be * C1),
+                     dS2_2 = __builtin_fma(al2, w2, be * C2);
         const double s = 1.0 / f0;
-        double sbar = gtbar;
+        double sbar = 0.0;
         sbar = __builtin_fma(gbar_in[1], dS1_0, sbar);
         sbar = __builtin_fma(gbar_in[2], dS1_1, sbar);
         sbar = __builtin_fma(gbar_in[3], dS1_2, sbar);
@@ -83,17 +91,42 @@ __device__ __forceinline__ void rhs_vjp(const Row& r, const TermConsts& tc, cons
         sbar = __builtin_fma(gbar_in[7], q * (dS1_0 + dS2_0), sbar);
         sbar = __builtin_fma(gbar_in[8], q * (dS1_1 + dS2_1), sbar);
         sbar = __builtin_fma(gbar_in[9], q * (dS1_2 + dS2_2), sbar);
+        sbar = __builtin_fma(gscale, sbar, gtbar);
+        const double gs = gscale * s;
 #pragma unroll
-        for (int c = 1; c < 10; ++c) fb[c] = gbar_in[c] * s;
+        for (int c = 1; c < 10; ++c) fb[c] = gbar_in[c] * gs;
         fb[0] = -(s * s) * sbar;
     } else {
 #pragma unroll
-        for (int c = 0; c < 10; ++c) fb[c] = gbar_in[c];
+        for (int c = 0; c < 10; ++c) fb[c] = gbar_in[c] * gscale;
     }
 
     // ---------------- reverse ----------------
-    // dL = q (dS1 + dS2)
-    const double qbar = fb[7] * (dS1_0 + dS2_0) + fb[8] * (dS1_1 + dS2_1) + fb[9] * (dS1_2 + dS2_2);
+    // The cross products and the spin derivatives are recomputed below rather
+    // than kept from the primal pass (fewer registers live across the VJP);
+    // the empty asm keeps the compiler from merging the two computations.
+    double ra0 = a0, ra1 = a1, ra2 = a2, rb0_ = b0, rb1_ = b1, rb2_ = b2, rL0 = L0, rL1 = L1, rL2 = L2;
+    __asm__ volatile("" : "+v"(ra0), "+v"(ra1), "+v"(ra2), "+v"(rb0_), "+v"(rb1_), "+v"(rb2_), "+v"(rL0),
+                     "+v"(rL1), "+v"(rL2));
+#define a0 ra0
+#define a1 ra1
+#define a2 ra2
+#define b0 rb0_
+#define b1 rb1_
+#define b2 rb2_
+#define L0 rL0
+#define L1 rL1
+#define L2 rL2
+    const double u0 = __builtin_fma(L1, a2, -L2 * a1), u1 = __builtin_fma(L2, a0, -L0 * a2),
+                 u2 = __builtin_fma(L0, a1, -L1 * a0);
+    const double w0 = __builtin_fma(L1, b2, -L2 * b1), w1 = __builtin_fma(L2, b0, -L0 * b2),
+                 w2 = __builtin_fma(L0, b1, -L1 * b0);
+    const double C0 = __builtin_fma(a1, b2, -a2 * b1), C1 = __builtin_fma(a2, b0, -a0 * b2),
+                 C2 = __builtin_fma(a0, b1, -a1 * b0);
+    // dL = q (dS1 + dS2), dS1 + dS2 = al1 u + al2 w
+    const double ds0 = __builtin_fma(al1, u0, al2 * w0), ds1 = __builtin_fma(al1, u1, al2 * w1),
+                 ds2 = __builtin_fma(al1, u2, al2 * w2);
+    const double qbar = fb[7] * ds0 + fb[8] * ds1 + fb[9] * ds2;
     const double s1b0 = __builtin_fma(q, fb[7], fb[1]), s1b1 = __builtin_fma(q, fb[8], fb[2]),
                  s1b2 = __builtin_fma(q, fb[9], fb[3]);
     const double s2b0 = __builtin_fma(q, fb[7], fb[4]), s2b1 = __builtin_fma(q, fb[8], fb[5]),
@@ -203,6 +236,15 @@ __device__ __forceinline__ void rhs_vjp(const Row& r, const TermConsts& tc, cons
     ybar[1] += ab0; ybar[2] += ab1; ybar[3] += ab2;
     ybar[4] += bb0; ybar[5] += bb1; ybar[6] += bb2;
     ybar[7] += Lb0; ybar[8] += Lb1; ybar[9] += Lb2;
+#undef a0
+#undef a1
+#undef a2
+#undef b0
+#undef b1
+#undef b2
+#undef L0
+#undef L1
+#undef L2
 }
 
 // ---------------------------------------------------------------------------

@@ -32,6 +32,15 @@
 #ifndef PN_WPE_F32
 #define PN_WPE_F32 3
 #endif
+// Where the backward pass parks the stage points Y_2..Y_6 (1: LDS, 0: a
+// global scratch row per lane) and the stage adjoints mu_2..mu_6 (1: LDS,
+// 0: registers); chosen by measurement.
+#ifndef PN_ADJ_Y_LDS
+#define PN_ADJ_Y_LDS 1
+#endif
+#ifndef PN_ADJ_MU_LDS
+#define PN_ADJ_MU_LDS 0
+#endif
 
 namespace pn {
 
@@ -673,14 +682,14 @@ struct AdjIo {
     double* __restrict__ g_L0;          // [3][ld]
     double* __restrict__ g_w0;          // [ld]
     double* __restrict__ ws;            // [n][K][10]
+    double* __restrict__ ystage;        // [60][n] (stage points outside LDS only)
     const int32_t* __restrict__ order;  // [n] or null
 };
 
-// the stage derivative: f (time mode) or g (omega mode, dt/domega in *gt)
-__device__ __forceinline__ void stage_deriv(const Row& R, const TermConsts& tc, const double* Y, double* k,
-                                            bool om) {
-    LogBase lb;
-    rhs<Row, false>(R, tc, lb, Y, k);
+// the stage derivative: f (time mode) or g (omega mode)
+__device__ __forceinline__ void stage_deriv(const Row& R, const TermConsts& tc, const LogBase& lb, const double* Y,
+                                            double* k, bool om) {
+    rhs<Row, true>(R, tc, lb, Y, k);
     if (om) {
         const double s = 1.0 / k[0];
 #pragma unroll
@@ -691,137 +700,155 @@ __device__ __forceinline__ void stage_deriv(const Row& R, const TermConsts& tc, 
 
 // one replayed step (no error control): y <- y + h sum b_i k_i
 __device__ __forceinline__ void replay_step(const Row& R, const TermConsts& tc, double* y, double h, bool om) {
+    const LogBase lb = log_base(R, y);
     double k1[10], k2[10], k3[10], k4[10], k5[10], k6[10], Y[10];
-    stage_deriv(R, tc, y, k1, om);
+    stage_deriv(R, tc, lb, y, k1, om);
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int c = 0; c < 10; ++c) Y[c] = __builtin_fma(h * A21, k1[c], y[c]);
-    stage_deriv(R, tc, Y, k2, om);
+    stage_deriv(R, tc, lb, Y, k2, om);
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int c = 0; c < 10; ++c) Y[c] = __builtin_fma(h * A32, k2[c], __builtin_fma(h * A31, k1[c], y[c]));
-    stage_deriv(R, tc, Y, k3, om);
+    stage_deriv(R, tc, lb, Y, k3, om);
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int c = 0; c < 10; ++c)
         Y[c] = __builtin_fma(h * A43, k3[c], __builtin_fma(h * A42, k2[c], __builtin_fma(h * A41, k1[c], y[c])));
-    stage_deriv(R, tc, Y, k4, om);
+    stage_deriv(R, tc, lb, Y, k4, om);
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int c = 0; c < 10; ++c)
         Y[c] = __builtin_fma(h * A54, k4[c], __builtin_fma(h * A53, k3[c],
                __builtin_fma(h * A52, k2[c], __builtin_fma(h * A51, k1[c], y[c]))));
-    stage_deriv(R, tc, Y, k5, om);
+    stage_deriv(R, tc, lb, Y, k5, om);
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int c = 0; c < 10; ++c)
         Y[c] = __builtin_fma(h * A65, k5[c], __builtin_fma(h * A64, k4[c], __builtin_fma(h * A63, k3[c],
                __builtin_fma(h * A62, k2[c], __builtin_fma(h * A61, k1[c], y[c])))));
-    stage_deriv(R, tc, Y, k6, om);
+    stage_deriv(R, tc, lb, Y, k6, om);
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int c = 0; c < 10; ++c)
         y[c] = __builtin_fma(h * B6, k6[c], __builtin_fma(h * B5, k5[c], __builtin_fma(h * B4, k4[c],
                __builtin_fma(h * B3, k3[c], __builtin_fma(h * B1, k1[c], y[c])))));
 }
 
-// Reverse of one step from state y (before the step).  lam (10) and the row
-// adjoint are updated in place; lt is dL/dt (constant along the path).
-// `last` marks the last omega-step, whose size depends on y[0].
-__device__ __forceinline__ void reverse_step(const Row& R, const TermConsts& tc, const double* y, double h, bool om,
-                                             bool last, double* lam, double lt, RowBar& rb) {
-    // forward stages (k1..k5 kept to rebuild the stage points in reverse)
-    double k1[10], k2[10], k3[10], k4[10], k5[10], Y[10];
-    stage_deriv(R, tc, y, k1, om);
+// Reverse of one step.  lam (10) and the row adjoint are updated in place;
+// lt is dL/dt (constant along the path).  `last` marks the last omega-step,
+// whose size D = omega_f - omega depends on the state: it adds -dL/dD to
+// lam[0].
+//   ys: the state before the step (slot 0, filled by the caller) and the
+//       stage points Y_2..Y_6 (slots 1..5) of this lane; entry (s, c) at
+//       ys[(s * 10 + c) * ystride] (a global scratch row per grid lane,
+//       coalesced across the wave);
+//   ms: the stage adjoints mu_2..mu_6 of this lane in LDS; entry (j, c) at
+//       ms[(j * 10 + c) * 64], j = 0..4 for mu_2..mu_6.
+__device__ __forceinline__ void reverse_step(const Row& R, const TermConsts& tc, double h, bool om, bool last,
+                                             double* lam, double lt, RowBar& rb, double* __restrict__ ys,
+                                             int64_t ystride, double* __restrict__ ms) {
+#define YS(S, C) ys[((S) * 10 + (C)) * ystride]
+#if PN_ADJ_MU_LDS
+#define MS(J, C) ms[((J) * 10 + (C)) * 64]
+#else
+    double mreg[5][10];
+#define MS(J, C) mreg[J][C]
+    (void)ms;
+#endif
+    LogBase lb;
+    {
+        double y[10];
 #pragma unroll
-    for (int c = 0; c < 10; ++c) Y[c] = __builtin_fma(h * A21, k1[c], y[c]);
-    stage_deriv(R, tc, Y, k2, om);
+        for (int c = 0; c < 10; ++c) y[c] = YS(0, c);
+        lb = log_base(R, y);
+        double k1[10], k2[10], k3[10], k4[10], k5[10], Y[10];
+        stage_deriv(R, tc, lb, y, k1, om);
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int c = 0; c < 10; ++c) Y[c] = __builtin_fma(h * A32, k2[c], __builtin_fma(h * A31, k1[c], y[c]));
-    stage_deriv(R, tc, Y, k3, om);
+        for (int c = 0; c < 10; ++c) { Y[c] = __builtin_fma(h * A21, k1[c], y[c]); YS(1, c) = Y[c]; }
+        stage_deriv(R, tc, lb, Y, k2, om);
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int c = 0; c < 10; ++c)
-        Y[c] = __builtin_fma(h * A43, k3[c], __builtin_fma(h * A42, k2[c], __builtin_fma(h * A41, k1[c], y[c])));
-    stage_deriv(R, tc, Y, k4, om);
+        for (int c = 0; c < 10; ++c) {
+            Y[c] = __builtin_fma(h * A32, k2[c], __builtin_fma(h * A31, k1[c], y[c]));
+            YS(2, c) = Y[c];
+        }
+        stage_deriv(R, tc, lb, Y, k3, om);
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int c = 0; c < 10; ++c)
-        Y[c] = __builtin_fma(h * A54, k4[c], __builtin_fma(h * A53, k3[c],
-               __builtin_fma(h * A52, k2[c], __builtin_fma(h * A51, k1[c], y[c]))));
-    stage_deriv(R, tc, Y, k5, om);
+        for (int c = 0; c < 10; ++c) {
+            Y[c] = __builtin_fma(h * A43, k3[c], __builtin_fma(h * A42, k2[c], __builtin_fma(h * A41, k1[c], y[c])));
+            YS(3, c) = Y[c];
+        }
+        stage_deriv(R, tc, lb, Y, k4, om);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int c = 0; c < 10; ++c) {
+            Y[c] = __builtin_fma(h * A54, k4[c], __builtin_fma(h * A53, k3[c],
+                   __builtin_fma(h * A52, k2[c], __builtin_fma(h * A51, k1[c], y[c]))));
+            YS(4, c) = Y[c];
+        }
+        stage_deriv(R, tc, lb, Y, k5, om);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int c = 0; c < 10; ++c)
+            YS(5, c) = __builtin_fma(h * A65, k5[c], __builtin_fma(h * A64, k4[c],
+                       __builtin_fma(h * A63, k3[c], __builtin_fma(h * A62, k2[c],
+                       __builtin_fma(h * A61, k1[c], y[c])))));
+    }
 
-    // reverse: stage i = 6 .. 1, mu_j kept for j > i
-    double mu6[10], mu5[10], mu4[10], mu3[10], mu2[10], Lb[10];
+    // reverse: stage i = 6 .. 1; mu_j (j > i) read back from LDS
     double lnew[10];
 #pragma unroll
     for (int c = 0; c < 10; ++c) lnew[c] = lam[c];
     double dh = 0.0;     // dL/dh (last omega-step only)
 
-    auto stage = [&](const double* Yi, const double* Lam_over_h, double bi, double* mu) {
-        // Lam_over_h = b_i lam + sum_{j>i} a_ji mu_j ; Lambda_i = h * that
-        double Lam[10], gi[10];
-#pragma unroll
-        for (int c = 0; c < 10; ++c) { Lam[c] = h * Lam_over_h[c]; mu[c] = 0.0; }
-        rhs_vjp(R, tc, Yi, Lam, lt * h * bi, om, mu, rb);
-        if (last) {
-            // dL/dh = sum_i k_i . (b_i lam + sum_{j>i} a_ji mu_j) + lt sum_i b_i dt/domega(Y_i)
-            stage_deriv(R, tc, Yi, gi, om);
-            double dot = 0.0;
-#pragma unroll
-            for (int c = 0; c < 10; ++c) dot = __builtin_fma(gi[c], Lam_over_h[c], dot);
-            LogBase lb;
-            double f[10];
-            rhs<Row, false>(R, tc, lb, Yi, f);
-            dh += dot + lt * bi / f[0];
-        }
-#pragma unroll
-        for (int c = 0; c < 10; ++c) lnew[c] += mu[c];
-    };
+    // Lh = b_i lam + sum_{j>i} a_ji mu_j ; the VJP is seeded with h Lh
+#define PN_REV_STAGE(SLOT, BI, MUJ, LAMEXPR)                                                      \
+    {                                                                                            \
+        double Yi[10], Lh[10], mu[10];                                                           \
+        _Pragma("unroll") for (int c = 0; c < 10; ++c) {                                         \
+            Yi[c] = YS(SLOT, c);                                                                 \
+            Lh[c] = (LAMEXPR);                                                                   \
+            mu[c] = 0.0;                                                                         \
+        }                                                                                        \
+        rhs_vjp(R, tc, lb, Yi, Lh, h, lt * h * (BI), om, mu, rb);                                \
+        if (last) {                                                                              \
+            double f[10];                                                                        \
+            rhs<Row, true>(R, tc, lb, Yi, f);                                                    \
+            const double s = 1.0 / f[0];                                                         \
+            double dot = Lh[0];                                                                  \
+            _Pragma("unroll") for (int c = 1; c < 10; ++c) dot = __builtin_fma(f[c] * s, Lh[c], dot); \
+            dh += dot + lt * (BI) * s;                                                           \
+        }                                                                                        \
+        _Pragma("unroll") for (int c = 0; c < 10; ++c) {                                         \
+            lnew[c] += mu[c];                                                                    \
+            if ((MUJ) >= 0) MS(MUJ, c) = mu[c];                                                  \
+        }                                                                                        \
+        __builtin_amdgcn_sched_barrier(0);                                                       \
+    }
 
-    // stage 6
-#pragma unroll
-    for (int c = 0; c < 10; ++c)
-        Y[c] = __builtin_fma(h * A65, k5[c], __builtin_fma(h * A64, k4[c], __builtin_fma(h * A63, k3[c],
-               __builtin_fma(h * A62, k2[c], __builtin_fma(h * A61, k1[c], y[c])))));
-#pragma unroll
-    for (int c = 0; c < 10; ++c) Lb[c] = B6 * lam[c];
-    stage(Y, Lb, B6, mu6);
-    // stage 5
-#pragma unroll
-    for (int c = 0; c < 10; ++c)
-        Y[c] = __builtin_fma(h * A54, k4[c], __builtin_fma(h * A53, k3[c],
-               __builtin_fma(h * A52, k2[c], __builtin_fma(h * A51, k1[c], y[c]))));
-#pragma unroll
-    for (int c = 0; c < 10; ++c) Lb[c] = __builtin_fma(A65, mu6[c], B5 * lam[c]);
-    stage(Y, Lb, B5, mu5);
-    // stage 4
-#pragma unroll
-    for (int c = 0; c < 10; ++c)
-        Y[c] = __builtin_fma(h * A43, k3[c], __builtin_fma(h * A42, k2[c], __builtin_fma(h * A41, k1[c], y[c])));
-#pragma unroll
-    for (int c = 0; c < 10; ++c) Lb[c] = __builtin_fma(A64, mu6[c], __builtin_fma(A54, mu5[c], B4 * lam[c]));
-    stage(Y, Lb, B4, mu4);
-    // stage 3
-#pragma unroll
-    for (int c = 0; c < 10; ++c) Y[c] = __builtin_fma(h * A32, k2[c], __builtin_fma(h * A31, k1[c], y[c]));
-#pragma unroll
-    for (int c = 0; c < 10; ++c)
-        Lb[c] = __builtin_fma(A63, mu6[c], __builtin_fma(A53, mu5[c], __builtin_fma(A43, mu4[c], B3 * lam[c])));
-    stage(Y, Lb, B3, mu3);
-    // stage 2 (b2 = 0)
-#pragma unroll
-    for (int c = 0; c < 10; ++c) Y[c] = __builtin_fma(h * A21, k1[c], y[c]);
-#pragma unroll
-    for (int c = 0; c < 10; ++c)
-        Lb[c] = __builtin_fma(A62, mu6[c], __builtin_fma(A52, mu5[c], __builtin_fma(A42, mu4[c], A32 * mu3[c])));
-    stage(Y, Lb, 0.0, mu2);
-    // stage 1 (Y_1 = y)
-#pragma unroll
-    for (int c = 0; c < 10; ++c)
-        Lb[c] = __builtin_fma(A61, mu6[c], __builtin_fma(A51, mu5[c], __builtin_fma(A41, mu4[c],
-                __builtin_fma(A31, mu3[c], __builtin_fma(A21, mu2[c], B1 * lam[c])))));
-    double mu1[10];
-    stage(y, Lb, B1, mu1);
+    PN_REV_STAGE(5, B6, 4, B6 * lam[c])
+    PN_REV_STAGE(4, B5, 3, __builtin_fma(A65, MS(4, c), B5 * lam[c]))
+    PN_REV_STAGE(3, B4, 2, __builtin_fma(A64, MS(4, c), __builtin_fma(A54, MS(3, c), B4 * lam[c])))
+    PN_REV_STAGE(2, B3, 1, __builtin_fma(A63, MS(4, c), __builtin_fma(A53, MS(3, c),
+                             __builtin_fma(A43, MS(2, c), B3 * lam[c]))))
+    PN_REV_STAGE(1, 0.0, 0, __builtin_fma(A62, MS(4, c), __builtin_fma(A52, MS(3, c),
+                              __builtin_fma(A42, MS(2, c), A32 * MS(1, c)))))
+    PN_REV_STAGE(0, B1, -1, __builtin_fma(A61, MS(4, c), __builtin_fma(A51, MS(3, c), __builtin_fma(A41, MS(2, c),
+                              __builtin_fma(A31, MS(1, c), __builtin_fma(A21, MS(0, c), B1 * lam[c]))))))
+#undef PN_REV_STAGE
+#undef YS
+#undef MS
 
 #pragma unroll
     for (int c = 0; c < 10; ++c) lam[c] = lnew[c];
-    if (last) lam[0] -= dh;      // D = omega_f - omega_n
+    if (last) lam[0] -= dh;
 }
 
-__device__ void adjoint_one(const AdjIo& io, const AdjUni& u, int64_t idx) {
+__device__ void adjoint_one(const AdjIo& io, const AdjUni& u, int64_t idx, double* ys, int64_t ystride,
+                            double* ms) {
     const int64_t ld = u.ld;
     const int st = io.status[idx];
     const double* tp = u.tape + idx * u.tape_stride;
@@ -870,12 +897,16 @@ __device__ void adjoint_one(const AdjIo& io, const AdjUni& u, int64_t idx) {
             }
         }
         for (int k = k1 - 1; k >= k0; --k) {
+            double w0 = 0.0;
 #pragma unroll
-            for (int c = 0; c < 10; ++c) y[c] = ws[(k - k0) * 10 + c];
+            for (int c = 0; c < 10; ++c) {
+                const double v = ws[(k - k0) * 10 + c];
+                ys[c * ystride] = v;
+                if (c == 0) w0 = v;
+            }
             const bool om = k >= nt;
             const bool last = om && k == N - 1;
-            const double h = last ? u.omega_f - y[0] : hs[k];
-            reverse_step(R, u.tc, y, h, om, last, lam, lt, rb);
+            reverse_step(R, u.tc, last ? u.omega_f - w0 : hs[k], om, last, lam, lt, rb, ys, ystride, ms);
         }
     }
     // chain the row adjoint to the masses
@@ -900,10 +931,26 @@ __device__ void adjoint_one(const AdjIo& io, const AdjUni& u, int64_t idx) {
 
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void adjoint_kernel(AdjIo io, AdjUni u) {
+#if PN_ADJ_MU_LDS
+    __shared__ double s_mu[BLOCK / 64][50][64];     // stage adjoints mu_2..mu_6 of each lane
+    double* ms = &s_mu[threadIdx.x / 64][0][lane_id()];
+#else
+    double* ms = nullptr;
+#endif
+#if PN_ADJ_Y_LDS
+    __shared__ double s_ys[BLOCK / 64][60][64];     // y and the stage points of each lane
+    double* ys = &s_ys[threadIdx.x / 64][0][lane_id()];
+    const int64_t ystride = 64;
+#endif
     const int64_t j = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
     if (j >= u.n) return;
     const int64_t idx = io.order ? (int64_t)io.order[j] : j;
-    adjoint_one(io, u, idx);
+#if !PN_ADJ_Y_LDS
+    // the stage-point scratch row of grid lane j: entry e at ystage[e * n + j]
+    double* ys = io.ystage + j;
+    const int64_t ystride = u.n;
+#endif
+    adjoint_one(io, u, idx, ys, ystride, ms);
 }
 
 __global__ void reset_counter(unsigned long long* c) { *c = 0ull; }
@@ -1133,7 +1180,9 @@ int pn_integrate_record(int64_t n, int64_t ld, const double* m, const double* S0
 
 size_t pn_adjoint_workspace_bytes(int64_t n, int32_t ckpt_every) {
     if (n < 0 || ckpt_every < 1) return 0;
-    return (size_t)n * (size_t)ckpt_every * 10 * sizeof(double);
+    // the replayed states of one segment per inspiral, plus the stage points
+    // when those are not kept in LDS
+    return (size_t)n * ((size_t)ckpt_every * 10 + (PN_ADJ_Y_LDS ? 0 : 60)) * sizeof(double);
 }
 
 int pn_integrate_adjoint(int64_t n, int64_t ld, const double* m, double omega_f, const pn_opts* opt,
@@ -1168,7 +1217,9 @@ int pn_integrate_adjoint(int64_t n, int64_t ld, const double* m, double omega_f,
     u.ckpt_every = ckpt_every;
     AdjIo io;
     io.m = m; io.status = status; io.gy = gy_final; io.gt = gt_final;
-    io.g_m = g_m; io.g_S0 = g_S0; io.g_L0 = g_L0; io.g_w0 = g_omega0; io.ws = workspace; io.order = order;
+    io.g_m = g_m; io.g_S0 = g_S0; io.g_L0 = g_L0; io.g_w0 = g_omega0; io.order = order;
+    io.ws = workspace;                                       // [n][K][10] replayed segment states
+    io.ystage = PN_ADJ_Y_LDS ? nullptr : workspace + n * (int64_t)ckpt_every * 10;   // [60][n] stage points
     const int64_t grid = (n + 127) / 128;
     hipLaunchKernelGGL(adjoint_kernel<128>, dim3((unsigned)grid), dim3(128), 0, (hipStream_t)stream, io, u);
     return hipGetLastError() == hipSuccess ? PN_OK : PN_EHIP;
