@@ -152,18 +152,6 @@ __device__ __forceinline__ double error_norm(const Uni& u, const double* y, cons
     return z * 0.1;
 }
 
-// step factor after an accepted step with error z (safety 0.9, exponent 1/5,
-// clamped to [0.2, 5], no growth right after a rejection)
-__device__ __forceinline__ double accept_factor(double z, bool last_rej) {
-    const double zc = __builtin_fmin(__builtin_fmax(z, 9.313225746154785e-10), 1.073741824e9);
-    double fac = __builtin_fmin(5.0, __builtin_fmax(0.2, 0.9 * pow_m_tenth(zc)));
-    return last_rej ? __builtin_fmin(fac, 1.0) : fac;
-}
-
-__device__ __forceinline__ double reject_factor(double z) {
-    return __builtin_fmax(0.2, 0.9 * pow_m_tenth(__builtin_fmin(z, 1.073741824e9)));
-}
-
 // omega-mode: divide the RHS by omega-dot and put 1 in the omega slot.
 template <class T>
 __device__ __forceinline__ void to_omega_variable(T* k, T& dt, bool om) {
@@ -172,6 +160,94 @@ __device__ __forceinline__ void to_omega_variable(T* k, T& dt, bool om) {
     for (int c = 1; c < 10; ++c) k[c] *= s;
     k[0] = om ? T(1) : k[0];
     dt = s;
+}
+
+__device__ __forceinline__ double* tape_of(const Uni& u, int64_t idx) { return u.tape + idx * u.tape_stride; }
+
+__device__ __forceinline__ void tape_checkpoint(const Uni& u, int64_t idx, int j, const double* y) {
+    double* ck = tape_of(u, idx) + 2 + u.tape_cap + (int64_t)j * 10;
+#pragma unroll
+    for (int c = 0; c < 10; ++c) ck[c] = y[c];
+}
+
+// Outcome known before a step (in this order of precedence): the step limit,
+// a full tape, d omega/dt <= 0.
+template <bool RECORD, class LaneT>
+__device__ __forceinline__ int pre_status(const Uni& u, const LaneT& L) {
+    int st = 0;
+    if (L.omega_mode ? L.dt1 <= 0 : (u.rr_on && L.k1[0] <= 0)) st = PN_ST_OMEGADOT_NONPOSITIVE;
+    if (RECORD && L.acc >= u.tape_cap) st = PN_ST_TAPE_FULL;
+    if (L.acc + L.rej >= u.max_steps) st = PN_ST_MAX_STEPS;
+    return st;
+}
+
+// The step to attempt, clipped to what is left of the omega stretch (or of
+// t_end); last = the clipped step ends the integration if accepted.
+template <class LaneT>
+__device__ __forceinline__ double clip_step(const Uni& u, const LaneT& L, bool& last) {
+    const double remain = L.omega_mode ? u.omega_f - L.y[0] : u.t_end - L.t;
+    last = (L.omega_mode || u.tend) && L.h >= remain;
+    return last ? remain : L.h;
+}
+
+// Acceptance test and state update of an attempted step of size h, applied
+// on lanes with go = (active, no status before the step); other lanes keep
+// their state.  Y: candidate state, k7/dt7: its derivative, dts = sum_j b_j
+// dt_j (omega mode).  Returns 0 (continue), 1 (finished OK) or a status.
+template <bool RECORD, class LaneT, class KT>
+__device__ __forceinline__ int control(const Uni& u, LaneT& L, bool go, int st, bool fin, double z, double h,
+                                       bool last, const double* Y, const KT* k7, KT dt7, KT dts) {
+    if (go && !fin) st = PN_ST_NONFINITE;
+    const bool ok = go && fin;
+    const bool acc = ok && (u.fixed || z <= Z_ACCEPT);
+    // a candidate past omega_f is discarded: the stretch is finished with
+    // omega as the independent variable
+    const bool to_w = acc && !L.omega_mode && !u.tend && Y[0] > u.omega_f;
+    const bool take = acc && !to_w;
+    const bool rej = ok && !acc;
+    // step factor (safety 0.9, exponent 1/5, clamped to [0.2, 5], no growth
+    // right after a rejection); one z^(-1/10) serves accepts and rejects
+    double fac = 1.0;
+    if (!u.fixed) {
+        const double p = 0.9 * pow_m_tenth(__builtin_fmin(__builtin_fmax(z, 9.313225746154785e-10), 1.073741824e9));
+        const double fa = __builtin_fmin(5.0, __builtin_fmax(0.2, p));
+        fac = rej ? __builtin_fmax(0.2, p) : (L.last_rej ? __builtin_fmin(fa, 1.0) : fa);
+    }
+    // The state is updated with selects rather than a divergent branch, so
+    // that y and k1 keep their registers across the loop.
+    if (__builtin_expect(__ballot(to_w) != 0, 0)) {
+        const KT s = to_w ? KT(1) / L.k1[0] : KT(1);
+#pragma unroll
+        for (int c = 1; c < 10; ++c) L.k1[c] *= s;
+        L.k1[0] = to_w ? KT(1) : L.k1[0];
+        L.dt1 = to_w ? s : L.dt1;
+        L.nt = to_w ? L.acc : L.nt;
+        L.h = to_w ? u.omega_f - L.y[0] : L.h;
+        L.last_rej = to_w ? false : L.last_rej;
+        L.omega_mode = L.omega_mode || to_w;
+    }
+    if (RECORD && take) {
+        tape_of(u, L.idx)[2 + L.acc] = h;
+        if ((L.acc + 1) % u.ckpt_every == 0) tape_checkpoint(u, L.idx, (L.acc + 1) / u.ckpt_every, Y);
+    }
+    const double tn = L.omega_mode ? __builtin_fma(h, (double)dts, L.t) : L.t + h;
+    const bool done = take && (last || (!L.omega_mode && !u.tend && Y[0] == u.omega_f));
+#pragma unroll
+    for (int c = 0; c < 10; ++c) {
+        L.y[c] = take ? Y[c] : L.y[c];
+        L.k1[c] = take ? k7[c] : L.k1[c];
+    }
+    if (done && L.omega_mode) L.y[0] = u.omega_f;
+    L.t = take ? tn : L.t;
+    L.dt1 = take ? dt7 : L.dt1;
+    L.acc += take ? 1 : 0;
+    L.rej += rej ? 1 : 0;
+    const bool resize = rej || (take && !done && !u.fixed);
+    L.h = resize ? h * fac : L.h;
+    L.last_rej = resize ? rej : L.last_rej;
+    const double scale = L.omega_mode ? __builtin_fabs(L.y[0]) : __builtin_fmax(1.0, __builtin_fabs(L.t));
+    if (rej && L.h < 1e-14 * scale) st = PN_ST_H_UNDERFLOW;
+    return st != 0 ? st : (done ? 1 : 0);
 }
 
 // ===========================================================================
@@ -188,14 +264,6 @@ struct LaneF64 {
     int nt;           // accepted time steps (recording only)
     bool omega_mode, last_rej;
 };
-
-__device__ __forceinline__ double* tape_of(const Uni& u, int64_t idx) { return u.tape + idx * u.tape_stride; }
-
-__device__ __forceinline__ void tape_checkpoint(const Uni& u, int64_t idx, int j, const double* y) {
-    double* ck = tape_of(u, idx) + 2 + u.tape_cap + (int64_t)j * 10;
-#pragma unroll
-    for (int c = 0; c < 10; ++c) ck[c] = y[c];
-}
 
 template <bool RECORD>
 struct F64 {
@@ -230,22 +298,14 @@ struct F64 {
         }
     }
 
-    // One attempted step; 0 = continue, 1 = finished OK, < 0 = status.
-    static __device__ __forceinline__ int step(const Uni& u, LaneT& L, bool any_w) {
-        if (L.acc + L.rej >= u.max_steps) return PN_ST_MAX_STEPS;
-        if (RECORD && L.acc >= u.tape_cap) return PN_ST_TAPE_FULL;
-        if (!L.omega_mode && u.rr_on && L.k1[0] <= 0.0) return PN_ST_OMEGADOT_NONPOSITIVE;
-        if (L.omega_mode && L.dt1 <= 0.0) return PN_ST_OMEGADOT_NONPOSITIVE;
-
-        double h = L.h;
-        bool last = false;
-        if (L.omega_mode) {
-            const double remain = u.omega_f - L.y[0];
-            if (h >= remain) { h = remain; last = true; }
-        } else if (u.tend) {
-            const double remain = u.t_end - L.t;
-            if (h >= remain) { h = remain; last = true; }
-        }
+    // One attempted step.  Every lane of the wave runs it; lanes that are not
+    // active compute on their stale state and change nothing.  Returns 0 =
+    // continue, 1 = finished OK, < 0 = status (meaningful on active lanes).
+    static __device__ __forceinline__ int step(const Uni& u, LaneT& L, bool active, bool any_w) {
+        const int st0 = pre_status<RECORD>(u, L);
+        const bool go = active && st0 == 0;
+        bool last;
+        const double h = clip_step(u, L, last);
 
         const Row& R = L.row;
         const double* y = L.y;
@@ -310,7 +370,7 @@ struct F64 {
         double k7[10], dt7 = 1.0;
         rhs<Row, true>(R, u.tc, lb, Y, k7);
         if (any_w) to_omega_variable(k7, dt7, L.omega_mode);
-        L.nrhs += 6;
+        L.nrhs += go ? 6 : 0;
 
         double z = 0.0;
         bool fin = true;
@@ -323,49 +383,7 @@ struct F64 {
         }
 #pragma unroll
         for (int c = 0; c < 10; ++c) fin = fin && finite(Y[c]);
-        if (!fin) return PN_ST_NONFINITE;
-
-        if (u.fixed || z <= Z_ACCEPT) {
-            if (!L.omega_mode && !u.tend && Y[0] > u.omega_f) {
-                // the candidate passes omega_f: discard it and finish the stretch
-                // with omega as the independent variable
-                L.omega_mode = true;
-                L.nt = L.acc;
-                const double s = 1.0 / L.k1[0];
-#pragma unroll
-                for (int c = 1; c < 10; ++c) L.k1[c] *= s;
-                L.k1[0] = 1.0;
-                L.dt1 = s;
-                L.h = u.omega_f - L.y[0];
-                L.last_rej = false;
-                return 0;
-            }
-            L.t = L.omega_mode ? __builtin_fma(h, dts, L.t) : L.t + h;
-#pragma unroll
-            for (int c = 0; c < 10; ++c) { L.y[c] = Y[c]; L.k1[c] = k7[c]; }
-            L.dt1 = dt7;
-            if (RECORD) {
-                tape_of(u, L.idx)[2 + L.acc] = h;
-                if ((L.acc + 1) % u.ckpt_every == 0) tape_checkpoint(u, L.idx, (L.acc + 1) / u.ckpt_every, L.y);
-            }
-            L.acc += 1;
-            if (!L.omega_mode && !u.tend && L.y[0] == u.omega_f) last = true;
-            if (last) {
-                if (L.omega_mode) L.y[0] = u.omega_f;
-                return 1;
-            }
-            if (!u.fixed) {
-                L.h = h * accept_factor(z, L.last_rej);
-                L.last_rej = false;
-            }
-            return 0;
-        }
-        L.rej += 1;
-        L.h = h * reject_factor(z);
-        L.last_rej = true;
-        const double scale = L.omega_mode ? __builtin_fabs(L.y[0]) : __builtin_fmax(1.0, __builtin_fabs(L.t));
-        if (L.h < 1e-14 * scale) return PN_ST_H_UNDERFLOW;
-        return 0;
+        return control<RECORD>(u, L, go, st0, fin, z, h, last, Y, k7, dt7, dts);
     }
 };
 
@@ -380,6 +398,7 @@ struct LaneF32 {
     RowF row;
     int64_t idx;
     int acc, rej, nrhs;
+    int nt;           // accepted time steps (unused: no tape in this mode)
     bool omega_mode, last_rej;
 };
 
@@ -411,20 +430,12 @@ struct F32Split {
         write_out(io, u, L.idx, L.y, L.t, L.acc, L.rej, L.nrhs, st);
     }
 
-    static __device__ __forceinline__ int step(const Uni& u, LaneT& L, bool any_w) {
-        if (L.acc + L.rej >= u.max_steps) return PN_ST_MAX_STEPS;
-        if (!L.omega_mode && u.rr_on && L.k1[0] <= 0.0f) return PN_ST_OMEGADOT_NONPOSITIVE;
-        if (L.omega_mode && L.dt1 <= 0.0f) return PN_ST_OMEGADOT_NONPOSITIVE;
-
-        double h = L.h;
-        bool last = false;
-        if (L.omega_mode) {
-            const double remain = u.omega_f - L.y[0];
-            if (h >= remain) { h = remain; last = true; }
-        } else if (u.tend) {
-            const double remain = u.t_end - L.t;
-            if (h >= remain) { h = remain; last = true; }
-        }
+    // One attempted step, run by every lane as in the FP64 lane.
+    static __device__ __forceinline__ int step(const Uni& u, LaneT& L, bool active, bool any_w) {
+        const int st0 = pre_status<false>(u, L);
+        const bool go = active && st0 == 0;
+        bool last;
+        const double h = clip_step(u, L, last);
 
         const RowF& R = L.row;
         const float* k1 = L.k1;
@@ -488,7 +499,7 @@ struct F32Split {
         float k7[10], dt7 = 1.0f;
         rhs_f32(R, u.tcf, Y, k7);
         if (any_w) to_omega_variable(k7, dt7, L.omega_mode);
-        L.nrhs += 6;
+        L.nrhs += go ? 6 : 0;
 
         // candidate state in FP64
         double ynew[10];
@@ -505,42 +516,7 @@ struct F32Split {
         }
 #pragma unroll
         for (int c = 0; c < 10; ++c) fin = fin && finite(ynew[c]) && __builtin_isfinite(k7[c]);
-        if (!fin) return PN_ST_NONFINITE;
-
-        if (u.fixed || z <= Z_ACCEPT) {
-            if (!L.omega_mode && !u.tend && ynew[0] > u.omega_f) {
-                L.omega_mode = true;
-                const float s = 1.0f / L.k1[0];
-#pragma unroll
-                for (int c = 1; c < 10; ++c) L.k1[c] *= s;
-                L.k1[0] = 1.0f;
-                L.dt1 = s;
-                L.h = u.omega_f - L.y[0];
-                L.last_rej = false;
-                return 0;
-            }
-            L.t = L.omega_mode ? __builtin_fma(h, (double)dts, L.t) : L.t + h;
-#pragma unroll
-            for (int c = 0; c < 10; ++c) { L.y[c] = ynew[c]; L.k1[c] = k7[c]; }
-            L.dt1 = dt7;
-            L.acc += 1;
-            if (!L.omega_mode && !u.tend && L.y[0] == u.omega_f) last = true;
-            if (last) {
-                if (L.omega_mode) L.y[0] = u.omega_f;
-                return 1;
-            }
-            if (!u.fixed) {
-                L.h = h * accept_factor(z, L.last_rej);
-                L.last_rej = false;
-            }
-            return 0;
-        }
-        L.rej += 1;
-        L.h = h * reject_factor(z);
-        L.last_rej = true;
-        const double scale = L.omega_mode ? __builtin_fabs(L.y[0]) : __builtin_fmax(1.0, __builtin_fabs(L.t));
-        if (L.h < 1e-14 * scale) return PN_ST_H_UNDERFLOW;
-        return 0;
+        return control<false>(u, L, go, st0, fin, z, h, last, ynew, k7, dt7, dts);
     }
 };
 
@@ -556,8 +532,7 @@ __device__ __forceinline__ uint64_t wave_ballot(bool p) { return __ballot(p); }
 template <class P>
 __device__ __forceinline__ void persistent_loop(const Io& io, const Uni& u, unsigned long long* counter) {
     const int lane = lane_id();
-    typename P::LaneT L;
-    L.idx = -1;
+    typename P::LaneT L{};      // idle lanes step on zeros and discard the result
     bool active = false;
     bool exhausted = false;     // wave-uniform
     for (;;) {
@@ -595,12 +570,10 @@ __device__ __forceinline__ void persistent_loop(const Io& io, const Uni& u, unsi
         }
         // ---- one step on every active lane ----------------------------------------
         const bool any_w = wave_ballot(active && L.omega_mode) != 0;
-        if (active) {
-            const int r = P::step(u, L, any_w);
-            if (r != 0) {
-                P::finish(io, u, L, r == 1 ? PN_ST_OK : r);
-                active = false;
-            }
+        const int r = P::step(u, L, active, any_w);
+        if (active && r != 0) {
+            P::finish(io, u, L, r == 1 ? PN_ST_OK : r);
+            active = false;
         }
     }
 }
@@ -608,18 +581,16 @@ __device__ __forceinline__ void persistent_loop(const Io& io, const Uni& u, unsi
 // One lane per inspiral, no refill: a wave runs until its longest inspiral ends.
 template <class P>
 __device__ __forceinline__ void static_loop(const Io& io, const Uni& u, int64_t idx) {
-    typename P::LaneT L;
+    typename P::LaneT L{};
     bool active = false;
     if (idx < u.n) active = P::load(io, u, L, idx) == 0;
     for (;;) {
         if (wave_ballot(active) == 0) break;
         const bool any_w = wave_ballot(active && L.omega_mode) != 0;
-        if (active) {
-            const int r = P::step(u, L, any_w);
-            if (r != 0) {
-                P::finish(io, u, L, r == 1 ? PN_ST_OK : r);
-                active = false;
-            }
+        const int r = P::step(u, L, active, any_w);
+        if (active && r != 0) {
+            P::finish(io, u, L, r == 1 ? PN_ST_OK : r);
+            active = false;
         }
     }
 }
