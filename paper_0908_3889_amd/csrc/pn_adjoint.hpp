@@ -24,6 +24,7 @@ struct RowBar {
 //   fbar_c = gbar_c s (c >= 1),  fbar_0 = -s^2 sbar.
 //
 // gscale multiplies gbar_in (the step size of the RK adjoint recurrence).
+template <bool FAST_LOG>
 __device__ __forceinline__ void rhs_vjp(const Row& r, const TermConsts& tc, const LogBase& lb,
                                         const double* __restrict__ y,
                                         const double* __restrict__ gbar_in, double gscale, double gtbar,
@@ -34,10 +35,12 @@ __device__ __forceinline__ void rhs_vjp(const Row& r, const TermConsts& tc, cons
     const double v = M * w;
     const double x = cbrt_real(v);
     double lnv;
-    {
+    if (FAST_LOG) {
         const double uu = (w - lb.w) * lb.iw;
         if (__builtin_fabs(uu) <= 0.125) lnv = lb.lnv + log1p_small(uu);
         else lnv = log_pos(__builtin_fabs(v));
+    } else {
+        lnv = log_pos(__builtin_fabs(v));
     }
     const double x2 = x * x;
     const double L0 = y[7], L1 = y[8], L2 = y[9];

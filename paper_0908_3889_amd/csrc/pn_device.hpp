@@ -14,6 +14,15 @@
 
 namespace pn {
 
+// a*b + c as the three-address FP64 FMA.  For Horner steps whose addend is a
+// constant held in a register: the compiler otherwise copies the constant
+// and uses the two-address form.
+__device__ __forceinline__ double fma3(double a, double b, double c) {
+    double d;
+    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "v"(c));
+    return d;
+}
+
 // ---------------------------------------------------------------------------
 // FP64 special functions.  Each states the range it accepts; the callers
 // guarantee or clamp it.
@@ -58,6 +67,14 @@ __device__ __forceinline__ double rcp_pos(double d) {
     r = __builtin_fma(r, e, r);
     e = __builtin_fma(-d, r, 1.0);
     return __builtin_fma(r, e, r);
+}
+
+// 1/d for d > 0 normal to about 12 ulp: hardware reciprocal (good to about
+// 2^-24 relative) and one Newton step.  For the error norm, which only
+// steers the step size.
+__device__ __forceinline__ double rcp_1step(double d) {
+    const double r = __builtin_amdgcn_rcp(d);
+    return __builtin_fma(r, __builtin_fma(-d, r, 1.0), r);
 }
 
 // natural log of v > 0 (normal or subnormal): v = 2^e m with m in [sqrt(1/2), sqrt(2)),
@@ -197,20 +214,37 @@ __device__ __forceinline__ double log1p_small(double u) {
     s = __builtin_fma(__builtin_fma(-s, d, u), rd, s);
     const double s2 = s * s;
     double p = 1.0 / 11.0;
-    p = __builtin_fma(p, s2, 1.0 / 9.0);
-    p = __builtin_fma(p, s2, 1.0 / 7.0);
-    p = __builtin_fma(p, s2, 1.0 / 5.0);
-    p = __builtin_fma(p, s2, 1.0 / 3.0);
+    p = fma3(p, s2, 1.0 / 9.0);
+    p = fma3(p, s2, 1.0 / 7.0);
+    p = fma3(p, s2, 1.0 / 5.0);
+    p = fma3(p, s2, 1.0 / 3.0);
     const double s2x = s + s;
     return __builtin_fma(s2x * s2, p, s2x);
 }
 
-// ln|M w| at the start of a step, for the stage logs: within a step the
-// stage omegas stay close to omega_n, so ln|M w_s| = ln|M w_n| + ln(1 + u),
-// u = (w_s - w_n)/w_n, with a short series; |u| > 1/8 (rejected or very
-// long steps) falls back to the full log.
+// exp(t) - 1 for |t| <= 0.045: t (1 + t/2! + ... + t^7/8!) (the first
+// dropped term, t^9/9!, is below 2e-18).
+__device__ __forceinline__ double expm1_small(double t) {
+    double p = 1.0 / 40320.0;
+    p = fma3(p, t, 1.0 / 5040.0);
+    p = fma3(p, t, 1.0 / 720.0);
+    p = fma3(p, t, 1.0 / 120.0);
+    p = fma3(p, t, 1.0 / 24.0);
+    p = fma3(p, t, 1.0 / 6.0);
+    p = __builtin_fma(p, t, 0.5);
+    p = __builtin_fma(p, t, 1.0);
+    return t * p;
+}
+
+// The base of the stage logs and cube roots at the start of a step: within
+// a step the stage omegas stay close to omega_n, so with u = (w_s - w_n)/w_n
+//   ln|M w_s| = ln|M w_n| + ln(1 + u),
+//   (M w_s)^{1/3} = (M w_n)^{1/3} exp(ln(1 + u) / 3),
+// each from a short series; |u| > 1/8 (rejected or very long steps) falls
+// back to the full log and cube root.
 struct LogBase {
     double lnv;    // ln|M w_n|
+    double x;      // (M w_n)^{1/3}
     double w;      // w_n
     double iw;     // 1/w_n
 };
@@ -235,13 +269,14 @@ __device__ __forceinline__ void rhs(const RowT& r, const TermConsts& tc, const L
                                     const double* __restrict__ y, double* __restrict__ d) {
     const double w = y[0];
     const double v = r[R_M] * w;
-    const double x = cbrt_real(v);
-    double lnv;
-    if (FAST_LOG) {
-        const double u = (w - lb.w) * lb.iw;
-        if (__builtin_fabs(u) <= 0.125) lnv = lb.lnv + log1p_small(u);
-        else lnv = log_pos(__builtin_fabs(v));
+    double x, lnv;
+    const double u = FAST_LOG ? (w - lb.w) * lb.iw : 1.0;
+    if (FAST_LOG && __builtin_fabs(u) <= 0.125) {
+        const double l1 = log1p_small(u);
+        lnv = lb.lnv + l1;
+        x = __builtin_fma(lb.x, expm1_small(l1 * (1.0 / 3.0)), lb.x);
     } else {
+        x = cbrt_real(v);
         lnv = log_pos(__builtin_fabs(v));
     }
     const double x2 = x * x;
@@ -295,6 +330,7 @@ __device__ __forceinline__ LogBase log_base(const RowT& r, const double* y) {
     LogBase lb;
     lb.w = y[0];
     lb.lnv = log_pos(__builtin_fabs(r[R_M] * y[0]));
+    lb.x = cbrt_real(r[R_M] * y[0]);
     lb.iw = 1.0 / y[0];
     return lb;
 }

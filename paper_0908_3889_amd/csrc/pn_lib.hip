@@ -41,6 +41,11 @@
 #ifndef PN_ADJ_MU_LDS
 #define PN_ADJ_MU_LDS 0
 #endif
+// 1: the backward pass evaluates stage logs and cube roots from the per-step
+// base as the forward does; 0: with the full functions (fewer live registers)
+#ifndef PN_ADJ_BASE
+#define PN_ADJ_BASE 0
+#endif
 
 namespace pn {
 
@@ -146,7 +151,7 @@ __device__ __forceinline__ double error_norm(const Uni& u, const double* y, cons
 #pragma unroll
     for (int c = 0; c < 10; ++c) {
         const double sc = __builtin_fma(u.tol, __builtin_fmax(__builtin_fabs(y[c]), __builtin_fabs(ynew[c])), u.tol);
-        const double q = e[c] * rcp_pos(sc);
+        const double q = e[c] * rcp_1step(sc);
         z = __builtin_fma(q, q, z);
     }
     return z * 0.1;
@@ -660,7 +665,7 @@ struct AdjIo {
 // the stage derivative: f (time mode) or g (omega mode)
 __device__ __forceinline__ void stage_deriv(const Row& R, const TermConsts& tc, const LogBase& lb, const double* Y,
                                             double* k, bool om) {
-    rhs<Row, true>(R, tc, lb, Y, k);
+    rhs<Row, PN_ADJ_BASE>(R, tc, lb, Y, k);
     if (om) {
         const double s = 1.0 / k[0];
 #pragma unroll
@@ -671,7 +676,8 @@ __device__ __forceinline__ void stage_deriv(const Row& R, const TermConsts& tc, 
 
 // one replayed step (no error control): y <- y + h sum b_i k_i
 __device__ __forceinline__ void replay_step(const Row& R, const TermConsts& tc, double* y, double h, bool om) {
-    const LogBase lb = log_base(R, y);
+    LogBase lb{};
+    if (PN_ADJ_BASE) lb = log_base(R, y);
     double k1[10], k2[10], k3[10], k4[10], k5[10], k6[10], Y[10];
     stage_deriv(R, tc, lb, y, k1, om);
     __builtin_amdgcn_sched_barrier(0);
@@ -727,12 +733,12 @@ __device__ __forceinline__ void reverse_step(const Row& R, const TermConsts& tc,
 #define MS(J, C) mreg[J][C]
     (void)ms;
 #endif
-    LogBase lb;
+    LogBase lb{};
     {
         double y[10];
 #pragma unroll
         for (int c = 0; c < 10; ++c) y[c] = YS(0, c);
-        lb = log_base(R, y);
+        if (PN_ADJ_BASE) lb = log_base(R, y);
         double k1[10], k2[10], k3[10], k4[10], k5[10], Y[10];
         stage_deriv(R, tc, lb, y, k1, om);
         __builtin_amdgcn_sched_barrier(0);
@@ -784,10 +790,10 @@ __device__ __forceinline__ void reverse_step(const Row& R, const TermConsts& tc,
             Lh[c] = (LAMEXPR);                                                                   \
             mu[c] = 0.0;                                                                         \
         }                                                                                        \
-        rhs_vjp(R, tc, lb, Yi, Lh, h, lt * h * (BI), om, mu, rb);                                \
+        rhs_vjp<PN_ADJ_BASE>(R, tc, lb, Yi, Lh, h, lt * h * (BI), om, mu, rb);                   \
         if (last) {                                                                              \
             double f[10];                                                                        \
-            rhs<Row, true>(R, tc, lb, Yi, f);                                                    \
+            rhs<Row, PN_ADJ_BASE>(R, tc, lb, Yi, f);                                             \
             const double s = 1.0 / f[0];                                                         \
             double dot = Lh[0];                                                                  \
             _Pragma("unroll") for (int c = 1; c < 10; ++c) dot = __builtin_fma(f[c] * s, Lh[c], dot); \
