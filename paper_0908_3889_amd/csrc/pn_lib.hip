@@ -158,9 +158,12 @@ __device__ __forceinline__ double error_norm(const Uni& u, const double* y, cons
 }
 
 // omega-mode: divide the RHS by omega-dot and put 1 in the omega slot.
+__device__ __forceinline__ double recip(double d) { return rcp_pos(d); }
+__device__ __forceinline__ float recip(float d) { return __builtin_amdgcn_rcpf(d); }
+
 template <class T>
 __device__ __forceinline__ void to_omega_variable(T* k, T& dt, bool om) {
-    const T s = om ? T(1) / k[0] : T(1);
+    const T s = om ? recip(k[0]) : T(1);
 #pragma unroll
     for (int c = 1; c < 10; ++c) k[c] *= s;
     k[0] = om ? T(1) : k[0];
@@ -261,6 +264,7 @@ __device__ __forceinline__ int control(const Uni& u, LaneT& L, bool go, int st, 
 struct LaneF64 {
     double y[10];
     double k1[10];
+    double lnv;       // ln|M omega| at y, carried from the stage that produced y
     double dt1;       // dt/d(variable) of k1: 1 in time mode, 1/omega-dot in omega mode
     double t, h;
     Row row;
@@ -285,7 +289,7 @@ struct F64 {
         L.h = u.fixed ? u.h_fixed : u.h0;
         make_row(L.row, m1, m2, u.terms, u.theta_literal);
         LogBase lb;
-        rhs<Row, false>(L.row, u.tc, lb, L.y, L.k1);
+        L.lnv = rhs<Row, false>(L.row, u.tc, lb, L.y, L.k1);
         L.dt1 = 1.0;
         L.nrhs = 1;
         L.nt = 0;
@@ -318,7 +322,11 @@ struct F64 {
         double Y[10], k2[10], k3[10], k4[10], k5[10], k6[10];
         double dtj;
         double dts = B1 * L.dt1;     // sum_j b_j dt_j, used in omega mode only
-        const LogBase lb = log_base(R, y);
+        LogBase lb;
+        lb.w = y[0];
+        lb.iw = rcp_pos(y[0]);
+        lb.lnv = L.lnv;
+        lb.x = cbrt_real(R[R_M] * y[0]);
         {
             const double c1 = h * A21;
 #pragma unroll
@@ -373,7 +381,7 @@ struct F64 {
             }
         }
         double k7[10], dt7 = 1.0;
-        rhs<Row, true>(R, u.tc, lb, Y, k7);
+        const double lnv7 = rhs<Row, true>(R, u.tc, lb, Y, k7);
         if (any_w) to_omega_variable(k7, dt7, L.omega_mode);
         L.nrhs += go ? 6 : 0;
 
@@ -388,7 +396,10 @@ struct F64 {
         }
 #pragma unroll
         for (int c = 0; c < 10; ++c) fin = fin && finite(Y[c]);
-        return control<RECORD>(u, L, go, st0, fin, z, h, last, Y, k7, dt7, dts);
+        const int acc0 = L.acc;
+        const int r = control<RECORD>(u, L, go, st0, fin, z, h, last, Y, k7, dt7, dts);
+        L.lnv = L.acc != acc0 ? lnv7 : L.lnv;
+        return r;
     }
 };
 
@@ -801,7 +812,7 @@ __device__ __forceinline__ void reverse_step(const Row& R, const TermConsts& tc,
         }                                                                                        \
         _Pragma("unroll") for (int c = 0; c < 10; ++c) {                                         \
             lnew[c] += mu[c];                                                                    \
-            if ((MUJ) >= 0) MS(MUJ, c) = mu[c];                                                  \
+            if ((MUJ) >= 0) MS((MUJ) >= 0 ? (MUJ) : 0, c) = mu[c];                               \
         }                                                                                        \
         __builtin_amdgcn_sched_barrier(0);                                                       \
     }
