@@ -162,6 +162,34 @@ def bench_adjoint(args, api, pop, d, w, step, stream) -> int:
     return 0
 
 
+def bench_sweep(args, api, population, stream) -> int:
+    """Throughput against the number of inspirals n = 2^8 .. 2^22 (one JSON
+    line): n copies of one inspiral (every lane in lock step, the paper's
+    Sec. IV set-up) and the first n inspirals of the heterogeneous workload."""
+    import torch
+    w = population.WORKLOADS[args.workload]
+    full = population.generate(w, 2 ** 22)
+    rows = []
+    for k in range(8, 23, 2):
+        n = 2 ** k
+        for kind, pop in (("replicated", population.replicate(full, n)),
+                          ("heterogeneous", population.subset(full, np.arange(n)))):
+            d = api.to_device(pop)
+            out = api.alloc_outputs(n)
+
+            def step():
+                api.pn_integrate(d["m"], d["S"], d["L"], d["omega0"], full["omega_f"], full["tol"],
+                                 out=out, stream=stream)
+            ms = _time(step, max(2, args.steps // 2), 1, stream)
+            ok = bool((out["status"] == 0).all())
+            rows.append({"n": n, "kind": kind, "kernel_ms": ms, "inspirals_per_s": n / (ms * 1e-3),
+                         "rhs_evals_per_s": float(out["steps"][2].to(torch.int64).sum()) / (ms * 1e-3),
+                         "all_ok": ok})
+            del d, out
+    print(json.dumps({"metric": "throughput vs n", "workload": w.name, "rows": rows}), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -177,6 +205,8 @@ def main() -> int:
     ap.add_argument("--adjoint", default=None,
                     help="comma-separated checkpoint spacings K: time the recorded forward and the "
                          "discrete adjoint of loss = sum S1.S2 + sum L_hat_z against the plain forward")
+    ap.add_argument("--sweep", action="store_true",
+                    help="throughput against n = 2^8 .. 2^22, replicated and heterogeneous inspirals")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run three plain device copies of 512 MiB (counter calibration)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -197,6 +227,8 @@ def main() -> int:
     from paper_0908_3889_amd import api, population
 
     torch.cuda.set_device(0)
+    if args.sweep:
+        return bench_sweep(args, api, population, torch.cuda.current_stream())
     w = population.WORKLOADS[args.workload]
     pop = population.generate(w)
     d = api.to_device(pop)

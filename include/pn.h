@@ -97,7 +97,9 @@ typedef struct pn_opts {
     int32_t waves_per_simd;/* persistent grid: waves per SIMD (1..8); 0 -> the
                               occupancy the kernel is compiled for (2 FP64, 3 FP32-split) */
     int32_t refill_min;    /* persistent: a wave refills once this many of its lanes
-                              are idle (1..64); 0 -> 1 */
+                              are idle (1..64), or all are; 0 -> 4 (each refill pass
+                              costs the whole wave, so refilling in small batches
+                              beats refilling every lane at once) */
     int32_t precision;     /* PN_PREC_*; 0 -> FP64 */
 } pn_opts;
 

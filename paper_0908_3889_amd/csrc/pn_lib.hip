@@ -385,15 +385,13 @@ struct F64 {
         if (any_w) to_omega_variable(k7, dt7, L.omega_mode);
         L.nrhs += go ? 6 : 0;
 
-        double z = 0.0;
-        bool fin = true;
-        if (!u.fixed) {
-            double e[10];
+        // the error norm is formed in fixed-step mode too (and ignored there),
+        // which keeps it in the same block as its operands
+        double e[10];
 #pragma unroll
-            for (int c = 0; c < 10; ++c) e[c] = h * __builtin_fma(E7, k7[c], Ep[c]);
-            z = error_norm(u, y, Y, e);
-            fin = !__builtin_isnan(z);
-        }
+        for (int c = 0; c < 10; ++c) e[c] = h * __builtin_fma(E7, k7[c], Ep[c]);
+        const double z = error_norm(u, y, Y, e);
+        bool fin = u.fixed || !__builtin_isnan(z);
 #pragma unroll
         for (int c = 0; c < 10; ++c) fin = fin && finite(Y[c]);
         const int acc0 = L.acc;
@@ -521,15 +519,11 @@ struct F32Split {
         double ynew[10];
 #pragma unroll
         for (int c = 0; c < 10; ++c) ynew[c] = L.y[c] + (double)D[c];
-        double z = 0.0;
-        bool fin = true;
-        if (!u.fixed) {
-            double e[10];
+        double e[10];
 #pragma unroll
-            for (int c = 0; c < 10; ++c) e[c] = (double)(hf * __builtin_fmaf((float)E7, k7[c], Ep[c]));
-            z = error_norm(u, L.y, ynew, e);
-            fin = !__builtin_isnan(z);
-        }
+        for (int c = 0; c < 10; ++c) e[c] = (double)(hf * __builtin_fmaf((float)E7, k7[c], Ep[c]));
+        const double z = error_norm(u, L.y, ynew, e);
+        bool fin = u.fixed || !__builtin_isnan(z);
 #pragma unroll
         for (int c = 0; c < 10; ++c) fin = fin && finite(ynew[c]) && __builtin_isfinite(k7[c]);
         return control<false>(u, L, go, st0, fin, z, h, last, ynew, k7, dt7, dts);
@@ -1091,7 +1085,7 @@ static int integrate_impl(int64_t n, int64_t ld, const double* m, const double* 
     const int wps = o.waves_per_simd ? o.waves_per_simd
                                      : (o.precision == PN_PREC_FP32_SPLIT ? PN_WPE_F32 : PN_WPE_F64);
     if (wps < 1 || wps > 8) return PN_EINVAL;
-    const int refill = o.refill_min ? o.refill_min : 1;
+    const int refill = o.refill_min ? o.refill_min : 4;
     if (refill < 1 || refill > 64) return PN_EINVAL;
     if (o.terms < 0 || o.terms > PN_TERM_ALL) return PN_EINVAL;
     if (o.theta_literal != 0 && o.theta_literal != 1) return PN_EINVAL;

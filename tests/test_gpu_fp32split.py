@@ -63,7 +63,7 @@ def test_fp32split_fixed_step_against_fp64_oracle():
 def test_fp32split_launch_shapes_agree_bitwise():
     pop = P.generate("batching_4M", 1500)
     base = run_gpu(pop, precision="fp32split")
-    for kw in (dict(schedule="static"), dict(block=64), dict(waves_per_simd=1), dict(refill_min=16)):
+    for kw in (dict(schedule="static"), dict(block=64), dict(waves_per_simd=1), dict(refill_min=1), dict(refill_min=16)):
         other = run_gpu(pop, precision="fp32split", **kw)
         for k in ("y", "t", "steps", "status", "dots"):
             np.testing.assert_array_equal(other[k], base[k], err_msg=f"{kw} {k}")

@@ -188,7 +188,7 @@ def test_schedules_and_launch_shapes_agree_bitwise():
     pop = P.generate("batching_4M", 3001)
     base = run_gpu(pop)
     for kw in (dict(schedule="static"), dict(block=64), dict(block=128, waves_per_simd=1),
-               dict(waves_per_simd=4), dict(refill_min=8), dict(block=64, waves_per_simd=1)):
+               dict(waves_per_simd=4), dict(refill_min=1), dict(refill_min=8), dict(block=64, waves_per_simd=1)):
         other = run_gpu(pop, **kw)
         for k in ("y", "t", "steps", "status", "dots"):
             np.testing.assert_array_equal(other[k], base[k], err_msg=f"{kw} {k}")
