@@ -186,7 +186,16 @@ def bench_sweep(args, api, population, stream) -> int:
                          "rhs_evals_per_s": float(out["steps"][2].to(torch.int64).sum()) / (ms * 1e-3),
                          "all_ok": ok})
             del d, out
-    print(json.dumps({"metric": "throughput vs n", "workload": w.name, "rows": rows}), flush=True)
+    # the oracle on one host core, on copies of the same inspiral (the
+    # paper's CPU figure is one core, Sec. IV)
+    import oracle
+    one = population.replicate(full, 256)
+    t0 = time.perf_counter()
+    oracle.integrate(one["m"], one["S"], one["L"], one["omega0"], full["omega_f"], full["tol"], nthreads=1)
+    dt = time.perf_counter() - t0
+    print(json.dumps({"metric": "throughput vs n", "workload": w.name, "rows": rows,
+                      "cpu_baseline": {"value": 256 / dt, "unit": "inspirals/s", "cores": 1, "kind": "oracle",
+                                       "sample": "256 copies of inspiral 0"}}), flush=True)
     return 0
 
 

@@ -76,6 +76,11 @@ WORKLOADS = {
         "paper_equal_mass", 4096, ("fixed", 1.0), ("fixed", 1.0, 1.0),
         ("fixed", 0.00395), 0.05, 5e-7, BASE_SEED + 10,
         notes="m_i=0.5, chi_i=1, omega 0.00395 -> 0.05, tol 5e-7 (Sec. V A)"),
+    "paper_timing": Workload(
+        "paper_timing", 4096, ("fixed", 1.0), ("fixed", 1.0, 1.0),
+        ("fixed", 0.004), 0.1, 5e-7, BASE_SEED + 11,
+        notes="m_i=0.5, chi_i=1, omega 0.004 -> 0.1, tol 5e-7: the timing run of Sec. IV "
+              "(one test inspiral, replicated)"),
 }
 
 
