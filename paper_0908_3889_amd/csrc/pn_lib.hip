@@ -662,7 +662,7 @@ struct AdjIo {
     double* __restrict__ g_S0;          // [6][ld]
     double* __restrict__ g_L0;          // [3][ld]
     double* __restrict__ g_w0;          // [ld]
-    double* __restrict__ ws;            // [n][K][10]
+    double* __restrict__ ws;            // [K][11][n]: per grid lane, the segment's states and steps
     double* __restrict__ ystage;        // [60][n] (stage points outside LDS only)
     const int32_t* __restrict__ order;  // [n] or null
 };
@@ -829,8 +829,11 @@ __device__ __forceinline__ void reverse_step(const Row& R, const TermConsts& tc,
     if (last) lam[0] -= dh;
 }
 
-__device__ void adjoint_one(const AdjIo& io, const AdjUni& u, int64_t idx, double* ys, int64_t ystride,
-                            double* ms) {
+// wsl: this grid lane's column of the segment workspace, entry (k, c) at
+// wsl[(k * 11 + c) * n] (c < 10: the state before step k of the segment,
+// c = 10: that step's size), so that a wave's accesses are coalesced.
+__device__ void adjoint_one(const AdjIo& io, const AdjUni& u, int64_t idx, double* wsl, double* ys,
+                            int64_t ystride, double* ms) {
     const int64_t ld = u.ld;
     const int st = io.status[idx];
     const double* tp = u.tape + idx * u.tape_stride;
@@ -861,7 +864,8 @@ __device__ void adjoint_one(const AdjIo& io, const AdjUni& u, int64_t idx, doubl
     const int K = u.ckpt_every;
     const double* hs = tp + 2;
     const double* ck = tp + 2 + u.tape_cap;
-    double* ws = io.ws + idx * (int64_t)K * 10;
+    const int64_t wstride = u.n;
+#define WS(K_, C_) wsl[((int64_t)(K_) * 11 + (C_)) * wstride]
     const int nseg = (N + K - 1) / K;
     for (int sg = nseg - 1; sg >= 0; --sg) {
         const int k0 = sg * K;
@@ -870,27 +874,23 @@ __device__ void adjoint_one(const AdjIo& io, const AdjUni& u, int64_t idx, doubl
 #pragma unroll
         for (int c = 0; c < 10; ++c) y[c] = ck[(int64_t)sg * 10 + c];
         for (int k = k0; k < k1; ++k) {
+            const bool om = k >= nt;
+            const double h = (om && k == N - 1) ? u.omega_f - y[0] : hs[k];
 #pragma unroll
-            for (int c = 0; c < 10; ++c) ws[(k - k0) * 10 + c] = y[c];
-            if (k + 1 < k1) {    // the state after the segment's last step is not needed
-                const bool om = k >= nt;
-                const double h = (om && k == N - 1) ? u.omega_f - y[0] : hs[k];
-                replay_step(R, u.tc, y, h, om);
-            }
+            for (int c = 0; c < 10; ++c) WS(k - k0, c) = y[c];
+            WS(k - k0, 10) = h;
+            if (k + 1 < k1) replay_step(R, u.tc, y, h, om);   // the state after the segment is not needed
         }
         for (int k = k1 - 1; k >= k0; --k) {
-            double w0 = 0.0;
 #pragma unroll
-            for (int c = 0; c < 10; ++c) {
-                const double v = ws[(k - k0) * 10 + c];
-                ys[c * ystride] = v;
-                if (c == 0) w0 = v;
-            }
+            for (int c = 0; c < 10; ++c) ys[c * ystride] = WS(k - k0, c);
+            const double h = WS(k - k0, 10);
             const bool om = k >= nt;
             const bool last = om && k == N - 1;
-            reverse_step(R, u.tc, last ? u.omega_f - w0 : hs[k], om, last, lam, lt, rb, ys, ystride, ms);
+            reverse_step(R, u.tc, h, om, last, lam, lt, rb, ys, ystride, ms);
         }
     }
+#undef WS
     // chain the row adjoint to the masses
     double gm[2];
 #pragma unroll
@@ -932,7 +932,7 @@ __global__ __launch_bounds__(BLOCK) void adjoint_kernel(AdjIo io, AdjUni u) {
     double* ys = io.ystage + j;
     const int64_t ystride = u.n;
 #endif
-    adjoint_one(io, u, idx, ys, ystride, ms);
+    adjoint_one(io, u, idx, io.ws + j, ys, ystride, ms);
 }
 
 __global__ void reset_counter(unsigned long long* c) { *c = 0ull; }
@@ -1164,7 +1164,7 @@ size_t pn_adjoint_workspace_bytes(int64_t n, int32_t ckpt_every) {
     if (n < 0 || ckpt_every < 1) return 0;
     // the replayed states of one segment per inspiral, plus the stage points
     // when those are not kept in LDS
-    return (size_t)n * ((size_t)ckpt_every * 10 + (PN_ADJ_Y_LDS ? 0 : 60)) * sizeof(double);
+    return (size_t)n * ((size_t)ckpt_every * 11 + (PN_ADJ_Y_LDS ? 0 : 60)) * sizeof(double);
 }
 
 int pn_integrate_adjoint(int64_t n, int64_t ld, const double* m, double omega_f, const pn_opts* opt,
@@ -1200,8 +1200,8 @@ int pn_integrate_adjoint(int64_t n, int64_t ld, const double* m, double omega_f,
     AdjIo io;
     io.m = m; io.status = status; io.gy = gy_final; io.gt = gt_final;
     io.g_m = g_m; io.g_S0 = g_S0; io.g_L0 = g_L0; io.g_w0 = g_omega0; io.order = order;
-    io.ws = workspace;                                       // [n][K][10] replayed segment states
-    io.ystage = PN_ADJ_Y_LDS ? nullptr : workspace + n * (int64_t)ckpt_every * 10;   // [60][n] stage points
+    io.ws = workspace;                                       // [K][11][n] replayed states and steps
+    io.ystage = PN_ADJ_Y_LDS ? nullptr : workspace + n * (int64_t)ckpt_every * 11;   // [60][n] stage points
     const int64_t grid = (n + 127) / 128;
     hipLaunchKernelGGL(adjoint_kernel<128>, dim3((unsigned)grid), dim3(128), 0, (hipStream_t)stream, io, u);
     return hipGetLastError() == hipSuccess ? PN_OK : PN_EHIP;
