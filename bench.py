@@ -101,6 +101,26 @@ def measured_traffic(kernel: str, workload: str):
         return None
 
 
+def opts_block(args) -> int:
+    return args.block or 256
+
+
+def kernel_resources(kernel: str, block: int):
+    """VGPRs, AGPRs, spills, scratch, LDS and occupancy of the timed kernel
+    instantiation, from the compiler's resource report of the build."""
+    from paper_0908_3889_amd import build
+    want = {"integrate_persistent_f64": f"integrate_persistent_f64ILi{block}ELb0E",
+            "integrate_persistent_f32s": f"integrate_persistent_f32sILi{block}E",
+            "integrate_static_f64": f"integrate_static_f64ILi{block}ELb0E",
+            "integrate_static_f32s": f"integrate_static_f32sILi{block}E"}.get(kernel)
+    for name, fields in build.resource_usage().items():
+        if want and want in name:
+            keep = ("VGPRs", "AGPRs", "ScratchSize [bytes/lane]", "Occupancy [waves/SIMD]", "VGPRs Spill",
+                    "SGPRs Spill", "LDS Size [bytes/block]")
+            return {k: int(fields[k]) for k in keep if k in fields and fields[k].lstrip("-").isdigit()}
+    return None
+
+
 def calibrate_copy() -> int:
     """Three device-to-device copies of COPY_CAL_BYTES each (the reference
     kernel for scaling the FETCH_SIZE / WRITE_SIZE counters)."""
@@ -283,6 +303,7 @@ def main() -> int:
     value = n * args.steps / wall
     kernel = f"integrate_{args.schedule}_{'f64' if precision == 'fp64' else 'f32s'}"
     traffic = measured_traffic(kernel, w.name)
+    resources = kernel_resources(kernel, opts_block(args))
     res = {
         "metric": METRIC,
         "value": value,
@@ -303,6 +324,7 @@ def main() -> int:
                      "unit": "TFLOP/s", "frac": achieved / peak,
                      "traffic": traffic},
         "kernel": kernel,
+        "kernel_resources": resources,
         "kernel_ms": avg_ms,
         "rhs_evals_per_s": float(steps[2].astype(np.int64).sum()) / (avg_ms * 1e-3),
         "attempted_steps": int(((steps[2].astype(np.int64) - 1) // 6).sum()),
