@@ -182,6 +182,38 @@ def bench_adjoint(args, api, pop, d, w, step, stream) -> int:
     return 0
 
 
+def bench_stats(args, api, w, pop, d, stream) -> int:
+    """Time the statistics stage of Sec. V over the workload's own final dot
+    products (one JSON line): each operation separately, inputs in HBM."""
+    import torch
+    out = api.pn_integrate(d["m"], d["S"], d["L"], d["omega0"], pop["omega_f"], pop["tol"], stream=stream)
+    y0 = torch.cat([d["omega0"][None], d["S"], d["L"]], 0).contiguous()
+    init = api.pn_observables(y0, stream=stream)
+    fin = out["dots"]
+    torch.cuda.synchronize()
+    n = pop["n"]
+    sig = api.pn_pearson(init, fin, stream=stream)[:, 3].contiguous()
+    ops = {
+        "histogram_20": lambda: api.pn_histogram(fin, 20, stream=stream),
+        "histogram_100": lambda: api.pn_histogram(fin, 100, stream=stream),
+        "histogram2d_79": lambda: api.pn_histogram2d(init, fin, 79, stream=stream),
+        "pearson": lambda: api.pn_pearson(init, fin, stream=stream),
+        "kde_201": lambda: api.pn_kde(fin, sig, 201, stream=stream),
+        "ks_uniform": lambda: api.pn_ks_uniform(fin, stream=stream),
+    }
+    res = {"metric": "statistics stage (Sec. V) per operation", "workload": w.name, "n": n, "components": 3,
+           "ms": {}, "GB_per_s_read": {}}
+    reads = {"histogram_20": 24 * n, "histogram_100": 24 * n, "histogram2d_79": 48 * n, "pearson": 96 * n,
+             "kde_201": 24 * n, "ks_uniform": 24 * n}
+    for k, f in ops.items():
+        ms = _time(f, args.steps, args.warmup, stream)
+        res["ms"][k] = ms
+        res["GB_per_s_read"][k] = reads[k] / (ms * 1e-3) / 1e9
+    res["kde_exp_per_s"] = 3 * n * 201 / (res["ms"]["kde_201"] * 1e-3)
+    print(json.dumps(res), flush=True)
+    return 0
+
+
 def bench_sweep(args, api, population, stream) -> int:
     """Throughput against the number of inspirals n = 2^8 .. 2^22 (one JSON
     line): n copies of one inspiral (every lane in lock step, the paper's
@@ -234,6 +266,8 @@ def main() -> int:
     ap.add_argument("--adjoint", default=None,
                     help="comma-separated checkpoint spacings K: time the recorded forward and the "
                          "discrete adjoint of loss = sum S1.S2 + sum L_hat_z against the plain forward")
+    ap.add_argument("--stats", action="store_true",
+                    help="time the statistics stage (histograms, Pearson r, KDE, K-S) on the workload's outputs")
     ap.add_argument("--sweep", action="store_true",
                     help="throughput against n = 2^8 .. 2^22, replicated and heterogeneous inspirals")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -273,6 +307,8 @@ def main() -> int:
 
     if args.adjoint:
         return bench_adjoint(args, api, pop, d, w, step, stream)
+    if args.stats:
+        return bench_stats(args, api, w, pop, d, stream)
 
     for _ in range(args.warmup):
         step()

@@ -196,6 +196,71 @@ int pn_integrate_adjoint(int64_t n, int64_t ld, const double* m, double omega_f,
                          double* g_m, double* g_S0, double* g_L0, double* g_omega0,
                          double* workspace, size_t ws_bytes, const int32_t* order, void* stream);
 
+/*
+ * The statistics of Sec. V over per-inspiral values, e.g. the dot products
+ * that pn_integrate writes to `dots` (final) and pn_observables gives for the
+ * initial state.  All arrays are device float64 SoA with leading dimension
+ * ld >= n; component c of entry i at x[c*ld + i], c < ncomp (1..16).  Every
+ * result is written to caller-owned device memory; results are deterministic
+ * (fixed reduction trees, independent of the device's CU count).  Return
+ * codes as for pn_integrate.  n = 0 writes zero counts and NaN for every
+ * floating result.
+ *
+ * pn_histogram -- counts[c][b] = number of entries with e_b <= x < e_{b+1},
+ * e_b = lo + b*(hi - lo)/nbins (computed as a product then a sum, e_nbins =
+ * hi, the last bin closed); entries outside [lo, hi] or NaN are not counted
+ * (Sec. V: 20 and 100 bins on [-1, 1]).  counts: int64 [ncomp][nbins],
+ * nbins 1..4096, lo < hi finite.
+ */
+int pn_histogram(int64_t n, int64_t ld, const double* x, int32_t ncomp, int32_t nbins, double lo, double hi,
+                 int64_t* counts, void* stream);
+
+/*
+ * pn_histogram2d -- the bivariate histogram of (x[c], y[c]) with the bins of
+ * pn_histogram in both dimensions (Sec. V: initial against final value, 79
+ * bins): counts int64 [ncomp][nbins (x)][nbins (y)], nbins 1..128; an entry
+ * counts only if both values are in [lo, hi].
+ */
+int pn_histogram2d(int64_t n, int64_t ld, const double* x, const double* y, int32_t ncomp, int32_t nbins,
+                   double lo, double hi, int64_t* counts, void* stream);
+
+/*
+ * pn_pearson -- for each component pair (x[c], y[c]): out[c][0..4] = mean x,
+ * mean y, standard deviation of x and of y (with 1/(n-1)), and the Pearson
+ * product-moment coefficient r (Sec. V), from two passes (means, then
+ * centred sums).  workspace: device buffer of pn_stats_workspace_bytes(n,
+ * ncomp, 0) bytes.  n = 1 gives NaN deviations and r.
+ */
+int pn_pearson(int64_t n, int64_t ld, const double* x, const double* y, int32_t ncomp, double* out,
+               void* workspace, size_t ws_bytes, void* stream);
+
+/*
+ * pn_kde -- the Gaussian kernel density estimator of Sec. V on ngrid points
+ * g_k = lo + k*(hi - lo)/(ngrid - 1):
+ *   out[c][k] = 1/(n h_c) sum_j exp(-(g_k - x[c][j])^2 / (2 h_c^2)) / sqrt(2 pi),
+ * with Silverman's bandwidth h_c = 1.06 sigma_c n^(-1/5); sigma_c is read
+ * from the device at sigma[c * sigma_stride] (e.g. the standard deviations
+ * that pn_pearson wrote: sigma = out + 2, stride 5).  ngrid 2..4096.
+ * workspace: pn_stats_workspace_bytes(n, ncomp, ngrid) bytes.
+ */
+int pn_kde(int64_t n, int64_t ld, const double* x, int32_t ncomp, const double* sigma, int64_t sigma_stride,
+           int32_t ngrid, double lo, double hi, double* out, void* workspace, size_t ws_bytes, void* stream);
+
+/*
+ * pn_ks_uniform -- the Kolmogorov-Smirnov test of each component against the
+ * uniform distribution on [lo, hi] (Sec. V): out[c][0] = D = max_i max(i/n -
+ * F(x_(i)), F(x_(i)) - (i-1)/n) over the sorted values, F(x) = (x - lo)/(hi - lo);
+ * out[c][1] = the asymptotic p-value P(K > sqrt(n) D) of the Kolmogorov
+ * distribution.  The values must not be NaN.  workspace:
+ * pn_ks_workspace_bytes(n) bytes (a sorted copy and the sort's scratch).
+ */
+size_t pn_ks_workspace_bytes(int64_t n);
+int pn_ks_uniform(int64_t n, int64_t ld, const double* x, int32_t ncomp, double lo, double hi, double* out,
+                  void* workspace, size_t ws_bytes, void* stream);
+
+/* Workspace bytes of pn_pearson (ngrid = 0) and pn_kde (ngrid > 0). */
+size_t pn_stats_workspace_bytes(int64_t n, int32_t ncomp, int32_t ngrid);
+
 /* Name of a PN_* return code (static string). */
 const char* pn_strerror(int code);
 

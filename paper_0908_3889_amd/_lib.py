@@ -26,7 +26,8 @@ PN_PREC_FP64, PN_PREC_FP32_SPLIT = 0, 1
 
 EXPORTS = ("pn_integrate", "pn_rhs", "pn_observables", "pn_strerror", "pn_version",
            "pn_tape_stride", "pn_integrate_record", "pn_adjoint_workspace_bytes",
-           "pn_integrate_adjoint")
+           "pn_integrate_adjoint", "pn_histogram", "pn_histogram2d", "pn_pearson", "pn_kde",
+           "pn_ks_workspace_bytes", "pn_ks_uniform", "pn_stats_workspace_bytes")
 
 
 class PnOpts(C.Structure):
@@ -83,6 +84,21 @@ def load():
     L.pn_integrate_adjoint.argtypes = [i64, i64, vp, dbl, popts, vp, i64, C.c_int32, vp, vp, vp, vp, vp,
                                        vp, vp, vp, C.c_size_t, vp, vp]
     L.pn_integrate_adjoint.restype = C.c_int
+    i32, sz = C.c_int32, C.c_size_t
+    L.pn_histogram.argtypes = [i64, i64, vp, i32, i32, dbl, dbl, vp, vp]
+    L.pn_histogram.restype = C.c_int
+    L.pn_histogram2d.argtypes = [i64, i64, vp, vp, i32, i32, dbl, dbl, vp, vp]
+    L.pn_histogram2d.restype = C.c_int
+    L.pn_pearson.argtypes = [i64, i64, vp, vp, i32, vp, vp, sz, vp]
+    L.pn_pearson.restype = C.c_int
+    L.pn_kde.argtypes = [i64, i64, vp, i32, vp, i64, i32, dbl, dbl, vp, vp, sz, vp]
+    L.pn_kde.restype = C.c_int
+    L.pn_ks_workspace_bytes.argtypes = [i64]
+    L.pn_ks_workspace_bytes.restype = sz
+    L.pn_ks_uniform.argtypes = [i64, i64, vp, i32, dbl, dbl, vp, vp, sz, vp]
+    L.pn_ks_uniform.restype = C.c_int
+    L.pn_stats_workspace_bytes.argtypes = [i64, i32, i32]
+    L.pn_stats_workspace_bytes.restype = sz
     _lib = L
     return L
 

@@ -224,6 +224,104 @@ def pn_observables(y, stream=None) -> torch.Tensor:
     return out
 
 
+# ---------------------------------------------------------------------------
+# the statistics of Sec. V
+# ---------------------------------------------------------------------------
+
+def _comp(x, name):
+    """A [ncomp, n] float64 device array with unit stride along n."""
+    if x.dim() == 1:
+        x = x.unsqueeze(0)
+    if x.dtype != torch.float64 or x.dim() != 2 or (x.shape[1] > 1 and x.stride(1) != 1):
+        raise ValueError(f"{name} must be a float64 [ncomp, n] array with unit stride along n")
+    return x
+
+
+def pn_histogram(x, nbins=20, lo=-1.0, hi=1.0, stream=None) -> torch.Tensor:
+    """Counts [ncomp, nbins] (int64) of x [ncomp, n] in equal bins on [lo, hi]."""
+    x = _comp(x, "x")
+    nc, n = int(x.shape[0]), int(x.shape[1])
+    out = torch.empty((nc, nbins), dtype=torch.int64, device=x.device)
+    rc = load().pn_histogram(n, _ld(x, n) if n else 0, C.c_void_p(x.data_ptr()), nc, int(nbins), float(lo),
+                             float(hi), C.c_void_p(out.data_ptr()), _stream(stream))
+    check(rc, "pn_histogram")
+    return out
+
+
+def pn_histogram2d(x, y, nbins=79, lo=-1.0, hi=1.0, stream=None) -> torch.Tensor:
+    """Bivariate counts [ncomp, nbins (x), nbins (y)] (int64)."""
+    x, y = _comp(x, "x"), _comp(y, "y")
+    nc, n = int(x.shape[0]), int(x.shape[1])
+    if tuple(y.shape) != tuple(x.shape) or (n and _ld(x, n) != _ld(y, n)):
+        raise ValueError("x and y must have one shape and leading dimension")
+    out = torch.empty((nc, nbins, nbins), dtype=torch.int64, device=x.device)
+    rc = load().pn_histogram2d(n, _ld(x, n) if n else 0, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()), nc,
+                               int(nbins), float(lo), float(hi), C.c_void_p(out.data_ptr()), _stream(stream))
+    check(rc, "pn_histogram2d")
+    return out
+
+
+def _workspace(nbytes, device):
+    return torch.empty(max(int(nbytes), 8), dtype=torch.uint8, device=device)
+
+
+def pn_pearson(x, y, stream=None) -> torch.Tensor:
+    """[ncomp, 5]: mean x, mean y, std x, std y (1/(n-1)), Pearson r."""
+    x, y = _comp(x, "x"), _comp(y, "y")
+    nc, n = int(x.shape[0]), int(x.shape[1])
+    if tuple(y.shape) != tuple(x.shape) or (n and _ld(x, n) != _ld(y, n)):
+        raise ValueError("x and y must have one shape and leading dimension")
+    out = torch.empty((nc, 5), dtype=torch.float64, device=x.device)
+    wb = int(load().pn_stats_workspace_bytes(n, nc, 0))
+    ws = _workspace(wb, x.device)
+    rc = load().pn_pearson(n, _ld(x, n) if n else 0, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()), nc,
+                           C.c_void_p(out.data_ptr()), C.c_void_p(ws.data_ptr()), wb, _stream(stream))
+    check(rc, "pn_pearson")
+    return out
+
+
+def pn_kde(x, sigma, ngrid=201, lo=-1.0, hi=1.0, stream=None) -> torch.Tensor:
+    """Gaussian KDE [ncomp, ngrid] on lo + k (hi - lo)/(ngrid - 1), bandwidth
+    1.06 sigma n^(-1/5); sigma: device [ncomp] (e.g. pn_pearson(...)[:, 2])."""
+    x = _comp(x, "x")
+    nc, n = int(x.shape[0]), int(x.shape[1])
+    if sigma.dtype != torch.float64 or sigma.numel() != nc or sigma.device != x.device:
+        raise ValueError("sigma must be a float64 device array of ncomp values")
+    out = torch.empty((nc, ngrid), dtype=torch.float64, device=x.device)
+    wb = int(load().pn_stats_workspace_bytes(n, nc, ngrid))
+    ws = _workspace(wb, x.device)
+    rc = load().pn_kde(n, _ld(x, n) if n else 0, C.c_void_p(x.data_ptr()), nc, C.c_void_p(sigma.data_ptr()),
+                       int(sigma.stride(0)) if sigma.dim() == 1 else 1, int(ngrid), float(lo), float(hi),
+                       C.c_void_p(out.data_ptr()), C.c_void_p(ws.data_ptr()), wb, _stream(stream))
+    check(rc, "pn_kde")
+    return out
+
+
+def pn_ks_uniform(x, lo=-1.0, hi=1.0, stream=None) -> torch.Tensor:
+    """[ncomp, 2]: the K-S statistic D against U[lo, hi] and its asymptotic p-value."""
+    x = _comp(x, "x")
+    nc, n = int(x.shape[0]), int(x.shape[1])
+    out = torch.empty((nc, 2), dtype=torch.float64, device=x.device)
+    wb = int(load().pn_ks_workspace_bytes(n))
+    ws = _workspace(wb, x.device)
+    rc = load().pn_ks_uniform(n, _ld(x, n) if n else 0, C.c_void_p(x.data_ptr()), nc, float(lo), float(hi),
+                              C.c_void_p(out.data_ptr()), C.c_void_p(ws.data_ptr()), wb, _stream(stream))
+    check(rc, "pn_ks_uniform")
+    return out
+
+
+def statistics(dots_initial, dots_final, nbins=20, nbins2d=79, ngrid=201, stream=None) -> dict:
+    """The statistics of Sec. V for the three unit-vector dot products:
+    histograms of the final values, the bivariate histograms and Pearson r of
+    initial against final, the KDE and the K-S test of the final values."""
+    p = pn_pearson(dots_initial, dots_final, stream=stream)
+    return {"hist": pn_histogram(dots_final, nbins, stream=stream),
+            "hist2d": pn_histogram2d(dots_initial, dots_final, nbins2d, stream=stream),
+            "pearson": p,
+            "kde": pn_kde(dots_final, p[:, 3].contiguous(), ngrid, stream=stream),
+            "ks": pn_ks_uniform(dots_final, stream=stream)}
+
+
 def to_device(pop: dict, device="cuda") -> dict:
     """The input arrays of a population (numpy, from population.generate) on the GPU."""
     return {k: torch.from_numpy(pop[k]).to(device) for k in ("m", "S", "L", "omega0")}

@@ -21,7 +21,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpn.so")
 RESOURCE_REPORT = os.path.join(HERE, "build_resource_usage.txt")
 
-SOURCES = [os.path.join(CSRC, "pn_lib.hip")]
+SOURCES = [os.path.join(CSRC, "pn_lib.hip"), os.path.join(CSRC, "pn_stats.hip")]
 
 
 def hipcc() -> str:
@@ -49,12 +49,16 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+# the sources the integration and adjoint kernels are compiled from
+KERNEL_SOURCES = ["pn_lib.hip", "pn_device.hpp", "pn_adjoint.hpp"]
+
+
 def source_digest() -> str:
-    """sha256 over the device sources and the C header (file names and bytes),
-    identifying the kernels that a stored counter reading was taken on."""
+    """sha256 over the sources of the integration kernels and the C header
+    (file names and bytes), identifying the kernels that a stored counter
+    reading was taken on."""
     h = hashlib.sha256()
-    files = sorted(f for f in os.listdir(CSRC) if f.endswith((".hip", ".hpp")))
-    for f in files + ["../../include/pn.h"]:
+    for f in KERNEL_SOURCES + ["../../include/pn.h"]:
         path = os.path.normpath(os.path.join(CSRC, f))
         h.update(os.path.basename(path).encode())
         with open(path, "rb") as fh:

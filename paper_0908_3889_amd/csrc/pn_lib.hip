@@ -1042,6 +1042,11 @@ hipError_t launch_forward(const Io& io, const Uni& u, int precision, int schedul
     return hipGetLastError();
 }
 
+int device_ready() {
+    DevCtx* ctx = nullptr;
+    return get_ctx(&ctx);
+}
+
 }  // namespace pn
 
 using namespace pn;
