@@ -314,7 +314,9 @@ struct F64 {
         const int st0 = pre_status<RECORD>(u, L);
         const bool go = active && st0 == 0;
         bool last;
-        const double h = clip_step(u, L, last);
+        // idle lanes take a step of zero: their stage points stay on their
+        // state, so they never send the wave down a slow path
+        const double h = active ? clip_step(u, L, last) : 0.0;
 
         const Row& R = L.row;
         const double* y = L.y;
@@ -449,7 +451,9 @@ struct F32Split {
         const int st0 = pre_status<false>(u, L);
         const bool go = active && st0 == 0;
         bool last;
-        const double h = clip_step(u, L, last);
+        // idle lanes take a step of zero: their stage points stay on their
+        // state, so they never send the wave down a slow path
+        const double h = active ? clip_step(u, L, last) : 0.0;
 
         const RowF& R = L.row;
         const float* k1 = L.k1;
@@ -542,7 +546,8 @@ __device__ __forceinline__ uint64_t wave_ballot(bool p) { return __ballot(p); }
 template <class P>
 __device__ __forceinline__ void persistent_loop(const Io& io, const Uni& u, unsigned long long* counter) {
     const int lane = lane_id();
-    typename P::LaneT L{};      // idle lanes step on zeros and discard the result
+    typename P::LaneT L{};      // idle lanes step on this state and discard the result
+    L.y[0] = 1.0;               // a positive omega keeps their arithmetic finite
     bool active = false;
     bool exhausted = false;     // wave-uniform
     for (;;) {
@@ -592,6 +597,7 @@ __device__ __forceinline__ void persistent_loop(const Io& io, const Uni& u, unsi
 template <class P>
 __device__ __forceinline__ void static_loop(const Io& io, const Uni& u, int64_t idx) {
     typename P::LaneT L{};
+    L.y[0] = 1.0;
     bool active = false;
     if (idx < u.n) active = P::load(io, u, L, idx) == 0;
     for (;;) {
