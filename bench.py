@@ -214,6 +214,24 @@ def bench_stats(args, api, w, pop, d, stream) -> int:
     return 0
 
 
+def bench_study(args, api, stream) -> int:
+    """The parameter studies of Sec. V B and C on the GPU (one JSON line):
+    Pearson r of initial against final dot products against m1 (chi = 1) and
+    against chi (m1 = m2), n inspirals per point."""
+    import torch
+    values = {"m1": [0.5, 0.55, 0.6, 0.65, 0.7, 0.75, 0.8, 0.85, 0.9],
+              "chi": [0.1, 0.2, 0.3, 0.4, 0.5, 0.6, 0.7, 0.8, 0.9, 1.0]}[args.study]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = api.pearson_study(args.study, values, n=args.study_n, stream=stream)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    print(json.dumps({"metric": f"Pearson r (initial vs final) against {args.study}", "n_per_point": args.study_n,
+                      "values": res["values"], "r_S1S2": res["r"][:, 0].tolist(), "r_S1L": res["r"][:, 1].tolist(),
+                      "r_S2L": res["r"][:, 2].tolist(), "all_ok": all(res["ok"]), "seconds": dt}), flush=True)
+    return 0
+
+
 def bench_sweep(args, api, population, stream) -> int:
     """Throughput against the number of inspirals n = 2^8 .. 2^22 (one JSON
     line): n copies of one inspiral (every lane in lock step, the paper's
@@ -268,6 +286,9 @@ def main() -> int:
                          "discrete adjoint of loss = sum S1.S2 + sum L_hat_z against the plain forward")
     ap.add_argument("--stats", action="store_true",
                     help="time the statistics stage (histograms, Pearson r, KDE, K-S) on the workload's outputs")
+    ap.add_argument("--study", default=None, choices=["m1", "chi"],
+                    help="Pearson r of initial vs final dot products against m1 or chi (Sec. V B, C)")
+    ap.add_argument("--study-n", type=int, default=65536)
     ap.add_argument("--sweep", action="store_true",
                     help="throughput against n = 2^8 .. 2^22, replicated and heterogeneous inspirals")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -292,6 +313,8 @@ def main() -> int:
     torch.cuda.set_device(0)
     if args.sweep:
         return bench_sweep(args, api, population, torch.cuda.current_stream())
+    if args.study:
+        return bench_study(args, api, torch.cuda.current_stream())
     w = population.WORKLOADS[args.workload]
     pop = population.generate(w)
     d = api.to_device(pop)

@@ -322,6 +322,41 @@ def statistics(dots_initial, dots_final, nbins=20, nbins2d=79, ngrid=201, stream
             "ks": pn_ks_uniform(dots_final, stream=stream)}
 
 
+def initial_dots(d: dict, stream=None) -> torch.Tensor:
+    """The dot products of the initial states of device inputs d (to_device)."""
+    y0 = torch.cat([d["omega0"][None], d["S"], d["L"]], 0).contiguous()
+    return pn_observables(y0, stream=stream)
+
+
+def pearson_study(kind: str, values, n: int = 16384, base: str = "paper_equal_mass", stream=None) -> dict:
+    """The parameter studies of Sec. V B and C: for each value, a population of
+    n inspirals of the base workload with m1 = value (chi_1 = chi_2 = 1) or
+    chi_1 = chi_2 = value (m1 = m2), integrated on the GPU, and the Pearson r
+    of initial against final S1.S2, S1.L, S2.L.  Returns {"values", "r" [k, 3],
+    "ok" [k]}."""
+    import dataclasses
+
+    import numpy as np
+
+    from . import population
+    w0 = population.WORKLOADS[base]
+    rs, oks = [], []
+    for v in values:
+        if kind == "m1":
+            w = dataclasses.replace(w0, q=("fixed", float(v) / (1.0 - float(v))), chi=("fixed", 1.0, 1.0))
+        elif kind == "chi":
+            w = dataclasses.replace(w0, q=("fixed", 1.0), chi=("fixed", float(v), float(v)))
+        else:
+            raise ValueError("kind is 'm1' or 'chi'")
+        pop = population.generate(w, n)
+        d = to_device(pop)
+        out = pn_integrate(d["m"], d["S"], d["L"], d["omega0"], pop["omega_f"], pop["tol"], stream=stream)
+        r = pn_pearson(initial_dots(d, stream=stream), out["dots"], stream=stream)[:, 4]
+        rs.append(r.cpu().numpy())
+        oks.append(bool((out["status"] == 0).all()))
+    return {"values": list(map(float, values)), "r": np.array(rs), "ok": oks}
+
+
 def to_device(pop: dict, device="cuda") -> dict:
     """The input arrays of a population (numpy, from population.generate) on the GPU."""
     return {k: torch.from_numpy(pop[k]).to(device) for k in ("m", "S", "L", "omega0")}

@@ -1,0 +1,71 @@
+"""The parameter studies of Sec. V B-D on the GPU: the Pearson r of initial
+against final dot products, against the oracle on the same populations and
+against the paper's statements."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import stats as S
+from paper_0908_3889_amd import population as P
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_0908_3889_amd import _lib
+    _lib.load()
+    yield
+
+
+def _oracle_r(w, n):
+    pop = P.generate(w, n)
+    r = oracle.integrate(pop["m"], pop["S"], pop["L"], pop["omega0"], pop["omega_f"], pop["tol"], nthreads=8)
+    assert (r["status"] == 0).all()
+    y0 = np.concatenate([pop["omega0"][None], pop["S"], pop["L"]])
+    d0, d1 = oracle.observables(y0), oracle.observables(r["y"])
+    return np.array([S.pearson(d0[k], d1[k])["r"] for k in range(3)])
+
+
+@pytest.mark.parametrize("kind,values", [("m1", [0.5, 0.7, 0.9]), ("chi", [0.1, 0.7])])
+def test_study_equals_oracle(kind, values):
+    from paper_0908_3889_amd import api
+    n = 1024
+    res = api.pearson_study(kind, values, n=n)
+    assert all(res["ok"])
+    base = P.WORKLOADS["paper_equal_mass"]
+    for i, v in enumerate(values):
+        if kind == "m1":
+            w = dataclasses.replace(base, q=("fixed", v / (1.0 - v)), chi=("fixed", 1.0, 1.0))
+        else:
+            w = dataclasses.replace(base, q=("fixed", 1.0), chi=("fixed", v, v))
+        # the final dot products agree to 1e-8, so r does to ~1e-8
+        np.testing.assert_allclose(res["r"][i], _oracle_r(w, n), rtol=0, atol=1e-6)
+
+
+def test_paper_statements():
+    """Sec. V B: r(S1.S2) falls as the masses become uneven (chi = 1); V C: it
+    stays above 0.98 for equal masses at every chi; V D: m1 = 0.4, chi = 0.05
+    gives r = -0.14."""
+    from paper_0908_3889_amd import api
+    m = api.pearson_study("m1", [0.5, 0.6, 0.7, 0.8], n=16384)["r"][:, 0]
+    # "falls quickly as the masses become uneven": down by more than 0.3 at
+    # m1 = 0.6, and no recovery further out
+    assert m[0] > 0.98 and m[1] < m[0] - 0.3 and (m[2:] < m[1]).all()
+    c = api.pearson_study("chi", [0.1, 0.4, 0.7, 1.0], n=16384)["r"][:, 0]
+    assert (c > 0.98).all()
+    r = api.pearson_study("m1", [0.4], n=16384)
+    # m1 = 0.4 with chi = 1 is the m1 study; the ring case has chi = 0.05
+    base = P.WORKLOADS["paper_equal_mass"]
+    w = dataclasses.replace(base, q=("fixed", 0.4 / 0.6), chi=("fixed", 0.05, 0.05))
+    pop = P.generate(w, 16384)
+    d = api.to_device(pop)
+    out = api.pn_integrate(d["m"], d["S"], d["L"], d["omega0"], pop["omega_f"], pop["tol"])
+    rr = api.pn_pearson(api.initial_dots(d), out["dots"])[0, 4].item()
+    assert abs(rr - (-0.14)) < 0.03
+    assert r["ok"][0]
