@@ -232,6 +232,30 @@ def bench_study(args, api, stream) -> int:
     return 0
 
 
+def bench_ks_run(args, api, stream) -> int:
+    """The K-S test of Sec. V at the paper's size: equal masses, chi_1 = chi_2
+    = 0.7, isotropic spins, the Sec. V A frequencies and tolerance
+    (omega 0.00395 -> 0.05, tol 5e-7), generated, integrated and tested on the
+    GPU in chunks (one JSON line)."""
+    import torch
+    from paper_0908_3889_amd import population
+    w = population.WORKLOADS["paper_equal_mass"]
+    spec = api.gen_spec(q=(1.0, 1.0), chi1=(0.7, 0.7), chi2=(0.7, 0.7), omega0=(w.omega0[1], w.omega0[1]),
+                        seed=population.BASE_SEED + 12)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = api.ks_run(args.ks_run, spec, w.omega_f, w.tol, chunk=1 << 24, stream=stream)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    print(json.dumps({"metric": "K-S test of the final S1_hat.S2_hat against U[-1, 1]", "n": args.ks_run,
+                      "D": res["ks"][0].item(), "p": res["ks"][1].item(), "not_ok": int(res["not_ok"]),
+                      "hist100": res["hist"].cpu().tolist(), "seconds": dt,
+                      "inspirals_per_s": args.ks_run / dt,
+                      "setup": "m1 = m2, chi = 0.7, omega 0.00395 -> 0.05, tol 5e-7, Philox seed 9083901"}),
+          flush=True)
+    return 0
+
+
 def bench_sweep(args, api, population, stream) -> int:
     """Throughput against the number of inspirals n = 2^8 .. 2^22 (one JSON
     line): n copies of one inspiral (every lane in lock step, the paper's
@@ -289,6 +313,9 @@ def main() -> int:
     ap.add_argument("--study", default=None, choices=["m1", "chi"],
                     help="Pearson r of initial vs final dot products against m1 or chi (Sec. V B, C)")
     ap.add_argument("--study-n", type=int, default=65536)
+    ap.add_argument("--ks-run", type=int, default=0,
+                    help="K-S test of the final S1.S2 over this many inspirals generated on the GPU "
+                         "(the paper's run: 362799815)")
     ap.add_argument("--sweep", action="store_true",
                     help="throughput against n = 2^8 .. 2^22, replicated and heterogeneous inspirals")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -315,6 +342,8 @@ def main() -> int:
         return bench_sweep(args, api, population, torch.cuda.current_stream())
     if args.study:
         return bench_study(args, api, torch.cuda.current_stream())
+    if args.ks_run:
+        return bench_ks_run(args, api, torch.cuda.current_stream())
     w = population.WORKLOADS[args.workload]
     pop = population.generate(w)
     d = api.to_device(pop)

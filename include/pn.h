@@ -261,6 +261,34 @@ int pn_ks_uniform(int64_t n, int64_t ld, const double* x, int32_t ncomp, double 
 /* Workspace bytes of pn_pearson (ngrid = 0) and pn_kde (ngrid > 0). */
 size_t pn_stats_workspace_bytes(int64_t n, int32_t ncomp, int32_t ngrid);
 
+/*
+ * On-device initial data (Sec. II, V): the population that pn_integrate takes,
+ * drawn on the GPU from the counter-based Philox4x64-10 generator (Salmon et
+ * al., SC11) with key (seed, 0).  Inspiral i (global index first + i) draws
+ * only from the blocks at counters (first + i, k, 0, 0): block 0 gives the
+ * uniforms u of q, chi_1, chi_2, omega0; blocks 1..32 the Marsaglia (1972)
+ * attempts for S_hat_1 (two per block), blocks 33..64 those for S_hat_2; a
+ * uniform is (x >> 11) 2^-53; after 64 rejected attempts S_hat = (0, 0, 1).
+ * Each parameter is lo + (hi - lo) u (fixed when lo == hi).  Then M = 1,
+ * m1 = q/(1 + q), m2 = 1/(1 + q), S_i = chi_i m_i^2 S_hat_i, L_hat = z.
+ * The same (seed, index) always gives the same inspiral, bit for bit,
+ * whatever n, first or the launch shape.
+ */
+typedef struct pn_gen_spec {
+    double   q_lo, q_hi;            /* mass ratio m1/m2 */
+    double   chi1_lo, chi1_hi;      /* Kerr parameters in [0, 1] */
+    double   chi2_lo, chi2_hi;
+    double   omega0_lo, omega0_hi;  /* initial orbital frequency (> 0) */
+    uint64_t seed;
+} pn_gen_spec;
+
+/* pn_generate -- write m [2][ld], S0 [6][ld], L0 [3][ld], omega0 [ld]
+ * (device, caller-owned) for inspirals first .. first + n - 1.
+ * PN_EINVAL for q_lo <= 0, chi outside [0, 1], omega0_lo <= 0, lo > hi or
+ * non-finite bounds. */
+int pn_generate(int64_t n, int64_t ld, int64_t first, const pn_gen_spec* spec, double* m, double* S0,
+                double* L0, double* omega0, void* stream);
+
 /* Name of a PN_* return code (static string). */
 const char* pn_strerror(int code);
 

@@ -27,7 +27,7 @@ PN_PREC_FP64, PN_PREC_FP32_SPLIT = 0, 1
 EXPORTS = ("pn_integrate", "pn_rhs", "pn_observables", "pn_strerror", "pn_version",
            "pn_tape_stride", "pn_integrate_record", "pn_adjoint_workspace_bytes",
            "pn_integrate_adjoint", "pn_histogram", "pn_histogram2d", "pn_pearson", "pn_kde",
-           "pn_ks_workspace_bytes", "pn_ks_uniform", "pn_stats_workspace_bytes")
+           "pn_ks_workspace_bytes", "pn_ks_uniform", "pn_stats_workspace_bytes", "pn_generate")
 
 
 class PnOpts(C.Structure):
@@ -44,6 +44,12 @@ class PnOpts(C.Structure):
         ("refill_min", C.c_int32),
         ("precision", C.c_int32),
     ]
+
+
+class PnGenSpec(C.Structure):
+    _fields_ = [("q_lo", C.c_double), ("q_hi", C.c_double), ("chi1_lo", C.c_double), ("chi1_hi", C.c_double),
+                ("chi2_lo", C.c_double), ("chi2_hi", C.c_double), ("omega0_lo", C.c_double),
+                ("omega0_hi", C.c_double), ("seed", C.c_uint64)]
 
 
 class PnError(RuntimeError):
@@ -99,6 +105,8 @@ def load():
     L.pn_ks_uniform.restype = C.c_int
     L.pn_stats_workspace_bytes.argtypes = [i64, i32, i32]
     L.pn_stats_workspace_bytes.restype = sz
+    L.pn_generate.argtypes = [i64, i64, i64, C.POINTER(PnGenSpec), vp, vp, vp, vp, vp]
+    L.pn_generate.restype = C.c_int
     _lib = L
     return L
 

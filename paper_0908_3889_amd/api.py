@@ -357,6 +357,56 @@ def pearson_study(kind: str, values, n: int = 16384, base: str = "paper_equal_ma
     return {"values": list(map(float, values)), "r": np.array(rs), "ok": oks}
 
 
+def gen_spec(q=(1.0, 1.0), chi1=(1.0, 1.0), chi2=(1.0, 1.0), omega0=(0.01, 0.01), seed=0) -> "_lib.PnGenSpec":
+    """The distribution pn_generate draws from: (lo, hi) per parameter, fixed
+    when lo == hi."""
+    return _lib.PnGenSpec(float(q[0]), float(q[1]), float(chi1[0]), float(chi1[1]), float(chi2[0]),
+                          float(chi2[1]), float(omega0[0]), float(omega0[1]), int(seed))
+
+
+def pn_generate(n: int, spec, first: int = 0, device="cuda", out=None, stream=None) -> dict:
+    """Inspirals first .. first + n - 1 of the Philox population `spec`
+    (gen_spec) drawn on the GPU: dict(m [2, n], S [6, n], L [3, n], omega0 [n])."""
+    if out is None:
+        out = {"m": torch.empty((2, n), dtype=torch.float64, device=device),
+               "S": torch.empty((6, n), dtype=torch.float64, device=device),
+               "L": torch.empty((3, n), dtype=torch.float64, device=device),
+               "omega0": torch.empty((n,), dtype=torch.float64, device=device)}
+    lds = {_ld(out[k], n) for k in ("m", "S", "L")} if n else {0}
+    if len(lds) != 1:
+        raise ValueError("the output arrays must share one leading dimension")
+    rc = load().pn_generate(n, lds.pop(), int(first), C.byref(spec), C.c_void_p(out["m"].data_ptr()),
+                            C.c_void_p(out["S"].data_ptr()), C.c_void_p(out["L"].data_ptr()),
+                            C.c_void_p(out["omega0"].data_ptr()), _stream(stream))
+    check(rc, "pn_generate")
+    return out
+
+
+def ks_run(total: int, spec, omega_f: float, tol: float, chunk: int = 1 << 22, nbins: int = 100,
+           stream=None) -> dict:
+    """The K-S test of Sec. V at scale, streamed on the GPU: chunks of
+    generate -> integrate, keeping only the final S1_hat.S2_hat of every
+    inspiral (8 B each), then the K-S statistic against U[-1, 1] and a
+    histogram over the whole sample.  No host traffic but the results."""
+    dev = "cuda"
+    chunk = min(chunk, total)
+    keep = torch.empty((1, total), dtype=torch.float64, device=dev)
+    pop = pn_generate(chunk, spec, 0, dev, stream=stream)
+    out = alloc_outputs(chunk, dev)
+    bad = torch.zeros((), dtype=torch.int64, device=dev)
+    for first in range(0, total, chunk):
+        n = min(chunk, total - first)
+        if n < chunk:
+            pop = {k: v[..., :n] for k, v in pop.items()}
+            out = {k: (v[..., :n] if v is not None else None) for k, v in out.items()}
+        pn_generate(n, spec, first, dev, out=pop, stream=stream)
+        pn_integrate(pop["m"], pop["S"], pop["L"], pop["omega0"], omega_f, tol, out=out, stream=stream)
+        keep[0, first:first + n].copy_(out["dots"][0])
+        bad += (out["status"] != 0).sum()
+    return {"n": total, "ks": pn_ks_uniform(keep, stream=stream)[0], "hist": pn_histogram(keep, nbins, stream=stream)[0],
+            "not_ok": bad, "final_s1s2": keep[0]}
+
+
 def to_device(pop: dict, device="cuda") -> dict:
     """The input arrays of a population (numpy, from population.generate) on the GPU."""
     return {k: torch.from_numpy(pop[k]).to(device) for k in ("m", "S", "L", "omega0")}

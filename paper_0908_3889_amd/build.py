@@ -21,7 +21,8 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpn.so")
 RESOURCE_REPORT = os.path.join(HERE, "build_resource_usage.txt")
 
-SOURCES = [os.path.join(CSRC, "pn_lib.hip"), os.path.join(CSRC, "pn_stats.hip")]
+SOURCES = [os.path.join(CSRC, "pn_lib.hip"), os.path.join(CSRC, "pn_stats.hip"),
+           os.path.join(CSRC, "pn_generate.hip")]
 
 
 def hipcc() -> str:
