@@ -46,6 +46,10 @@
 #ifndef PN_ADJ_BASE
 #define PN_ADJ_BASE 0
 #endif
+// the same choice for the replay of a segment (fewer values are live there)
+#ifndef PN_ADJ_REPLAY_BASE
+#define PN_ADJ_REPLAY_BASE 0
+#endif
 
 namespace pn {
 
@@ -674,9 +678,10 @@ struct AdjIo {
 };
 
 // the stage derivative: f (time mode) or g (omega mode)
+template <bool FAST = (PN_ADJ_BASE != 0)>
 __device__ __forceinline__ void stage_deriv(const Row& R, const TermConsts& tc, const LogBase& lb, const double* Y,
                                             double* k, bool om) {
-    rhs<Row, PN_ADJ_BASE>(R, tc, lb, Y, k);
+    rhs<Row, FAST>(R, tc, lb, Y, k);
     if (om) {
         const double s = 1.0 / k[0];
 #pragma unroll
@@ -688,34 +693,34 @@ __device__ __forceinline__ void stage_deriv(const Row& R, const TermConsts& tc, 
 // one replayed step (no error control): y <- y + h sum b_i k_i
 __device__ __forceinline__ void replay_step(const Row& R, const TermConsts& tc, double* y, double h, bool om) {
     LogBase lb{};
-    if (PN_ADJ_BASE) lb = log_base(R, y);
+    if (PN_ADJ_REPLAY_BASE) lb = log_base(R, y);
     double k1[10], k2[10], k3[10], k4[10], k5[10], k6[10], Y[10];
-    stage_deriv(R, tc, lb, y, k1, om);
+    stage_deriv<PN_ADJ_REPLAY_BASE != 0>(R, tc, lb, y, k1, om);
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int c = 0; c < 10; ++c) Y[c] = __builtin_fma(h * A21, k1[c], y[c]);
-    stage_deriv(R, tc, lb, Y, k2, om);
+    stage_deriv<PN_ADJ_REPLAY_BASE != 0>(R, tc, lb, Y, k2, om);
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int c = 0; c < 10; ++c) Y[c] = __builtin_fma(h * A32, k2[c], __builtin_fma(h * A31, k1[c], y[c]));
-    stage_deriv(R, tc, lb, Y, k3, om);
+    stage_deriv<PN_ADJ_REPLAY_BASE != 0>(R, tc, lb, Y, k3, om);
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int c = 0; c < 10; ++c)
         Y[c] = __builtin_fma(h * A43, k3[c], __builtin_fma(h * A42, k2[c], __builtin_fma(h * A41, k1[c], y[c])));
-    stage_deriv(R, tc, lb, Y, k4, om);
+    stage_deriv<PN_ADJ_REPLAY_BASE != 0>(R, tc, lb, Y, k4, om);
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int c = 0; c < 10; ++c)
         Y[c] = __builtin_fma(h * A54, k4[c], __builtin_fma(h * A53, k3[c],
                __builtin_fma(h * A52, k2[c], __builtin_fma(h * A51, k1[c], y[c]))));
-    stage_deriv(R, tc, lb, Y, k5, om);
+    stage_deriv<PN_ADJ_REPLAY_BASE != 0>(R, tc, lb, Y, k5, om);
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int c = 0; c < 10; ++c)
         Y[c] = __builtin_fma(h * A65, k5[c], __builtin_fma(h * A64, k4[c], __builtin_fma(h * A63, k3[c],
                __builtin_fma(h * A62, k2[c], __builtin_fma(h * A61, k1[c], y[c])))));
-    stage_deriv(R, tc, lb, Y, k6, om);
+    stage_deriv<PN_ADJ_REPLAY_BASE != 0>(R, tc, lb, Y, k6, om);
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int c = 0; c < 10; ++c)
