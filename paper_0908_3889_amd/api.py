@@ -140,6 +140,8 @@ def pn_integrate_adjoint(m, omega_f, rec: dict, gy, gt=None, opts: PnOpts | None
     _soa(m, 2, n, "m"); _soa(gy, 10, n, "gy")
     if gt is not None:
         _soa(gt, 1, n, "gt")
+    if n > 0 and (_ld(m, n) != n or _ld(gy, n) != n):
+        raise ValueError("m and gy must be contiguous (leading dimension n)")
     if order is not None:
         _soa(order, 1, n, "order", torch.int32)
     K = rec["ckpt_every"]
@@ -230,6 +232,8 @@ def pn_observables(y, stream=None) -> torch.Tensor:
 
 def _comp(x, name):
     """A [ncomp, n] float64 device array with unit stride along n."""
+    if not isinstance(x, torch.Tensor) or not x.is_cuda:
+        raise TypeError(f"{name} must be a torch tensor on the GPU")
     if x.dim() == 1:
         x = x.unsqueeze(0)
     if x.dtype != torch.float64 or x.dim() != 2 or (x.shape[1] > 1 and x.stride(1) != 1):
@@ -285,7 +289,8 @@ def pn_kde(x, sigma, ngrid=201, lo=-1.0, hi=1.0, stream=None) -> torch.Tensor:
     1.06 sigma n^(-1/5); sigma: device [ncomp] (e.g. pn_pearson(...)[:, 2])."""
     x = _comp(x, "x")
     nc, n = int(x.shape[0]), int(x.shape[1])
-    if sigma.dtype != torch.float64 or sigma.numel() != nc or sigma.device != x.device:
+    if not isinstance(sigma, torch.Tensor) or sigma.dtype != torch.float64 or sigma.numel() != nc \
+            or sigma.device != x.device:
         raise ValueError("sigma must be a float64 device array of ncomp values")
     out = torch.empty((nc, ngrid), dtype=torch.float64, device=x.device)
     wb = int(load().pn_stats_workspace_bytes(n, nc, ngrid))
@@ -372,6 +377,9 @@ def pn_generate(n: int, spec, first: int = 0, device="cuda", out=None, stream=No
                "S": torch.empty((6, n), dtype=torch.float64, device=device),
                "L": torch.empty((3, n), dtype=torch.float64, device=device),
                "omega0": torch.empty((n,), dtype=torch.float64, device=device)}
+    for k, c in (("m", 2), ("S", 6), ("L", 3)):
+        _soa(out[k], c, n, k)
+    _soa(out["omega0"], 1, n, "omega0")
     lds = {_ld(out[k], n) for k in ("m", "S", "L")} if n else {0}
     if len(lds) != 1:
         raise ValueError("the output arrays must share one leading dimension")
