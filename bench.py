@@ -101,10 +101,6 @@ def measured_traffic(kernel: str, workload: str):
         return None
 
 
-def opts_block(args) -> int:
-    return args.block or 256
-
-
 def kernel_resources(kernel: str, block: int):
     """VGPRs, AGPRs, spills, scratch, LDS and occupancy of the timed kernel
     instantiation, from the compiler's resource report of the build."""
@@ -320,6 +316,8 @@ def main() -> int:
                     help="throughput against n = 2^8 .. 2^22, replicated and heterogeneous inspirals")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run three plain device copies of 512 MiB (counter calibration)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="choose refill threshold and block size with pn_autotune on a 2^20 sample first")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     args = ap.parse_args()
@@ -352,6 +350,12 @@ def main() -> int:
     opts = api.make_opts(schedule=args.schedule, block=args.block, precision=precision,
                          waves_per_simd=args.waves_per_simd, refill_min=args.refill_min)
     stream = torch.cuda.current_stream()
+    tuned = None
+    if args.autotune:
+        opts, table = api.autotune(d["m"], d["S"], d["L"], d["omega0"], pop["omega_f"], pop["tol"], opts,
+                                   sample=1 << 20, stream=stream)
+        tuned = {"refill_min": opts.refill_min, "block": opts.block,
+                 "table_ms": {f"{r},{b}": v for (r, b), v in table.items()}}
 
     def step():
         api.pn_integrate(d["m"], d["S"], d["L"], d["omega0"], pop["omega_f"], pop["tol"], opts,
@@ -391,7 +395,7 @@ def main() -> int:
     value = n * args.steps / wall
     kernel = f"integrate_{args.schedule}_{'f64' if precision == 'fp64' else 'f32s'}"
     traffic = measured_traffic(kernel, w.name)
-    resources = kernel_resources(kernel, opts_block(args))
+    resources = kernel_resources(kernel, opts.block or 256)
     res = {
         "metric": METRIC,
         "value": value,
@@ -413,6 +417,8 @@ def main() -> int:
                      "traffic": traffic},
         "kernel": kernel,
         "kernel_resources": resources,
+        "launch": {"block": opts.block or 256, "refill_min": opts.refill_min or 4,
+                   "waves_per_simd": opts.waves_per_simd or None, "autotuned": tuned},
         "kernel_ms": avg_ms,
         "rhs_evals_per_s": float(steps[2].astype(np.int64).sum()) / (avg_ms * 1e-3),
         "attempted_steps": int(((steps[2].astype(np.int64) - 1) // 6).sum()),

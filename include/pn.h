@@ -135,6 +135,26 @@ int pn_integrate(int64_t n, int64_t ld,
                  double* dots, void* stream);
 
 /*
+ * pn_autotune -- choose the launch shape of pn_integrate for a population:
+ * times pn_integrate on its first `sample` inspirals (all n when sample <= 0
+ * or sample > n) for every candidate refill threshold {2, 3, 4, 6} and block
+ * size {128, 256} (waves per SIMD as compiled), `reps` times each (<= 0 ->
+ * 2) after one warm-up run, and writes the fastest to *best: a copy of *opt
+ * (or of the defaults when opt is NULL) with `block` and `refill_min` set.
+ * The outcome of an integration does not depend on the launch shape, so the
+ * choice only affects speed.  y_final .. dots: device outputs for the sample
+ * (caller-owned, leading dimension ld, at least the sample's entries); they
+ * hold an integration of the sample afterwards.  times_ms: optional host
+ * array of 8 doubles, each candidate's mean time in the order (refill, block)
+ * = (2,128), (2,256), (3,128), ... (6,256).  Unlike the other entry points
+ * this call blocks: it synchronises `stream` to read its timers.
+ */
+int pn_autotune(int64_t n, int64_t ld, const double* m, const double* S0, const double* L0,
+                const double* omega0, double omega_f, double tol, const pn_opts* opt, int64_t sample,
+                int32_t reps, double* y_final, double* t_final, int32_t* steps, int32_t* status,
+                double* dots, pn_opts* best, double* times_ms, void* stream);
+
+/*
  * pn_rhs -- Eqs. (1)-(4) evaluated pointwise, dy/dt at y, for testing the
  * right-hand side on its own.  m [2][ld], y [10][ld] -> dydt [10][ld].
  * `terms`/`theta_literal` as in pn_opts (opt may be NULL).

@@ -27,7 +27,8 @@ PN_PREC_FP64, PN_PREC_FP32_SPLIT = 0, 1
 EXPORTS = ("pn_integrate", "pn_rhs", "pn_observables", "pn_strerror", "pn_version",
            "pn_tape_stride", "pn_integrate_record", "pn_adjoint_workspace_bytes",
            "pn_integrate_adjoint", "pn_histogram", "pn_histogram2d", "pn_pearson", "pn_kde",
-           "pn_ks_workspace_bytes", "pn_ks_uniform", "pn_stats_workspace_bytes", "pn_generate")
+           "pn_ks_workspace_bytes", "pn_ks_uniform", "pn_stats_workspace_bytes", "pn_generate",
+           "pn_autotune")
 
 
 class PnOpts(C.Structure):
@@ -105,6 +106,9 @@ def load():
     L.pn_ks_uniform.restype = C.c_int
     L.pn_stats_workspace_bytes.argtypes = [i64, i32, i32]
     L.pn_stats_workspace_bytes.restype = sz
+    L.pn_autotune.argtypes = [i64, i64, vp, vp, vp, vp, dbl, dbl, popts, i64, i32, vp, vp, vp, vp, vp, popts,
+                              vp, vp]
+    L.pn_autotune.restype = C.c_int
     L.pn_generate.argtypes = [i64, i64, i64, C.POINTER(PnGenSpec), vp, vp, vp, vp, vp]
     L.pn_generate.restype = C.c_int
     _lib = L

@@ -98,6 +98,36 @@ def pn_integrate(m, S0, L0, omega0, omega_f, tol, opts: PnOpts | None = None, ou
     return out
 
 
+def autotune(m, S0, L0, omega0, omega_f, tol, opts: PnOpts | None = None, sample: int = 1 << 20,
+             reps: int = 2, stream=None):
+    """The fastest launch shape (refill threshold, block) of pn_integrate on
+    the first `sample` inspirals; returns (opts, {(refill, block): ms}).
+    Blocks until the timing runs are done."""
+    n = int(omega0.shape[0])
+    ns = n if sample <= 0 or sample > n else int(sample)
+    _soa(omega0, 1, n, "omega0")
+    _soa(m, 2, n, "m"); _soa(S0, 6, n, "S0"); _soa(L0, 3, n, "L0")
+    lds = {_ld(m, n), _ld(S0, n), _ld(L0, n)}
+    if n > 0 and len(lds) != 1:
+        raise ValueError("all [components, n] arrays must share one leading dimension")
+    ld = lds.pop() if n > 0 else 0
+    out = {"y": torch.empty((10, ld), dtype=torch.float64, device=omega0.device),
+           "t": torch.empty((ld,), dtype=torch.float64, device=omega0.device),
+           "steps": torch.empty((3, ld), dtype=torch.int32, device=omega0.device),
+           "status": torch.empty((ld,), dtype=torch.int32, device=omega0.device),
+           "dots": torch.empty((3, ld), dtype=torch.float64, device=omega0.device)}
+    best = PnOpts()
+    times = (C.c_double * 8)()
+    o = opts if opts is not None else make_opts()
+    p = lambda t: C.c_void_p(t.data_ptr())
+    rc = load().pn_autotune(n, ld, p(m), p(S0), p(L0), p(omega0), float(omega_f), float(tol), C.byref(o), ns,
+                            int(reps), p(out["y"]), p(out["t"]), p(out["steps"]), p(out["status"]), p(out["dots"]),
+                            C.byref(best), times, _stream(stream))
+    check(rc, "pn_autotune")
+    table = {(r, b): times[i] for i, (r, b) in enumerate((r, b) for r in (2, 3, 4, 6) for b in (128, 256))}
+    return best, table
+
+
 def _check_inputs(m, S0, L0, omega0):
     n = int(omega0.shape[0])
     _soa(omega0, 1, n, "omega0")

@@ -1162,6 +1162,54 @@ int pn_integrate(int64_t n, int64_t ld, const double* m, const double* S0, const
                           nullptr, 0, 0, stream);
 }
 
+int pn_autotune(int64_t n, int64_t ld, const double* m, const double* S0, const double* L0,
+                const double* omega0, double omega_f, double tol, const pn_opts* opt, int64_t sample,
+                int32_t reps, double* y_final, double* t_final, int32_t* steps, int32_t* status,
+                double* dots, pn_opts* best, double* times_ms, void* stream) {
+    if (!best || n < 0 || ld < n) return PN_EINVAL;
+    pn_opts base;
+    std::memset(&base, 0, sizeof(base));
+    if (opt) base = *opt;
+    const int64_t ns = (sample <= 0 || sample > n) ? n : sample;
+    const int r = reps > 0 ? reps : 2;
+    static const int kRefill[4] = {2, 3, 4, 6};
+    static const int kBlocks[2] = {128, 256};
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess) return PN_EHIP;
+    if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return PN_EHIP; }
+    int rc = PN_OK;
+    double best_ms = 0.0;
+    *best = base;
+    // warm-up with the base options (also validates every argument)
+    rc = pn_integrate(ns, ld, m, S0, L0, omega0, omega_f, tol, &base, y_final, t_final, steps, status, dots, stream);
+    for (int c = 0; c < 8 && rc == PN_OK; ++c) {
+        pn_opts o = base;
+        o.refill_min = kRefill[c / 2];
+        o.block = kBlocks[c % 2];
+        if (hipEventRecord(e0, s) != hipSuccess) { rc = PN_EHIP; break; }
+        for (int k = 0; k < r && rc == PN_OK; ++k)
+            rc = pn_integrate(ns, ld, m, S0, L0, omega0, omega_f, tol, &o, y_final, t_final, steps, status, dots,
+                              stream);
+        if (rc != PN_OK) break;
+        float ms = 0.0f;
+        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+            rc = PN_EHIP;
+            break;
+        }
+        const double mean = (double)ms / r;
+        if (times_ms) times_ms[c] = mean;
+        if (c == 0 || mean < best_ms) {
+            best_ms = mean;
+            *best = o;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return rc;
+}
+
 size_t pn_tape_stride(int64_t cap_steps, int32_t ckpt_every) {
     if (cap_steps < 1 || ckpt_every < 1) return 0;
     return (size_t)(2 + cap_steps + 10 * (cap_steps / ckpt_every + 1));
