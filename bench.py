@@ -216,7 +216,8 @@ def bench_study(args, api, stream) -> int:
     against chi (m1 = m2), n inspirals per point."""
     import torch
     values = {"m1": [0.5, 0.55, 0.6, 0.65, 0.7, 0.75, 0.8, 0.85, 0.9],
-              "chi": [0.1, 0.2, 0.3, 0.4, 0.5, 0.6, 0.7, 0.8, 0.9, 1.0]}[args.study]
+              "chi": [0.1, 0.2, 0.3, 0.4, 0.5, 0.6, 0.7, 0.8, 0.9, 1.0],
+              "omega0": [0.002, 0.003, 0.004, 0.005, 0.006, 0.008, 0.01, 0.015, 0.02]}[args.study]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     res = api.pearson_study(args.study, values, n=args.study_n, stream=stream)
@@ -306,8 +307,8 @@ def main() -> int:
                          "discrete adjoint of loss = sum S1.S2 + sum L_hat_z against the plain forward")
     ap.add_argument("--stats", action="store_true",
                     help="time the statistics stage (histograms, Pearson r, KDE, K-S) on the workload's outputs")
-    ap.add_argument("--study", default=None, choices=["m1", "chi"],
-                    help="Pearson r of initial vs final dot products against m1 or chi (Sec. V B, C)")
+    ap.add_argument("--study", default=None, choices=["m1", "chi", "omega0"],
+                    help="Pearson r of initial vs final dot products against m1, chi or omega0 (Sec. V B, C, D)")
     ap.add_argument("--study-n", type=int, default=65536)
     ap.add_argument("--ks-run", type=int, default=0,
                     help="K-S test of the final S1.S2 over this many inspirals generated on the GPU "

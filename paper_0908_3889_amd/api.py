@@ -365,8 +365,9 @@ def initial_dots(d: dict, stream=None) -> torch.Tensor:
 
 def pearson_study(kind: str, values, n: int = 16384, base: str = "paper_equal_mass", stream=None) -> dict:
     """The parameter studies of Sec. V B and C: for each value, a population of
-    n inspirals of the base workload with m1 = value (chi_1 = chi_2 = 1) or
-    chi_1 = chi_2 = value (m1 = m2), integrated on the GPU, and the Pearson r
+    n inspirals of the base workload with m1 = value (chi_1 = chi_2 = 1),
+    chi_1 = chi_2 = value (m1 = m2) or omega0 = value (the base workload
+    otherwise), integrated on the GPU, and the Pearson r
     of initial against final S1.S2, S1.L, S2.L.  Returns {"values", "r" [k, 3],
     "ok" [k]}."""
     import dataclasses
@@ -381,8 +382,10 @@ def pearson_study(kind: str, values, n: int = 16384, base: str = "paper_equal_ma
             w = dataclasses.replace(w0, q=("fixed", float(v) / (1.0 - float(v))), chi=("fixed", 1.0, 1.0))
         elif kind == "chi":
             w = dataclasses.replace(w0, q=("fixed", 1.0), chi=("fixed", float(v), float(v)))
+        elif kind == "omega0":
+            w = dataclasses.replace(w0, omega0=("fixed", float(v)))
         else:
-            raise ValueError("kind is 'm1' or 'chi'")
+            raise ValueError("kind is 'm1', 'chi' or 'omega0'")
         pop = population.generate(w, n)
         d = to_device(pop)
         out = pn_integrate(d["m"], d["S"], d["L"], d["omega0"], pop["omega_f"], pop["tol"], stream=stream)

@@ -69,3 +69,14 @@ def test_paper_statements():
     rr = api.pn_pearson(api.initial_dots(d), out["dots"])[0, 4].item()
     assert abs(rr - (-0.14)) < 0.03
     assert r["ok"][0]
+
+
+def test_equal_mass_correlation_insensitive_to_omega0():
+    """Sec. V D: outside the m1 = 0.4, chi = 0.05 case the results were
+    generally insensitive to omega0; for equal masses and chi = 1,
+    r(S1.S2) stays near 0.99 over omega0 = 0.003 .. 0.01."""
+    from paper_0908_3889_amd import api
+    res = api.pearson_study("omega0", [0.003, 0.00395, 0.006, 0.01], n=16384)
+    assert all(res["ok"])
+    r = res["r"][:, 0]
+    assert (r > 0.97).all() and r.max() - r.min() < 0.02
