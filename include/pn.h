@@ -21,7 +21,8 @@
  *    are read only; outputs are written for every i < n.
  *  - `stream` is a hipStream_t (NULL = the default stream).  Calls are
  *    asynchronous on that stream: they return once the work is enqueued.  The
- *    library never synchronises the device, prints or aborts.
+ *    library never synchronises the device (pn_autotune excepted: it reads
+ *    its timers), prints or aborts.
  *  - The return value is PN_OK (0) when the work was enqueued, or a negative
  *    PN_E* code: PN_EINVAL for bad arguments (nothing is launched),
  *    PN_ENODEV when no usable gfx950 device is current, PN_EHIP when a HIP
