@@ -53,7 +53,7 @@ def lib():
         vp, i64, i32, dbl = C.c_void_p, C.c_int64, C.c_int32, C.c_double
         L.oracle_rhs.argtypes = [i64, vp, vp, vp, i32, i32]
         L.oracle_integrate.argtypes = [i64, vp, vp, vp, vp, dbl, dbl, C.POINTER(_Opts),
-                                       vp, vp, vp, vp, vp, i32]
+                                       vp, vp, vp, vp, vp, vp, i32]
         L.oracle_tangent.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, vp, dbl, dbl,
                                      C.POINTER(_Opts), vp, vp, vp, vp, vp, i32]
         L.oracle_observables.argtypes = [i64, vp, vp]
@@ -95,13 +95,15 @@ def rhs(m, y, terms=TERM_ALL, theta_literal=0):
 
 def integrate(m, S0, L0, omega0, omega_f, tol, *, h0=0.0, h_fixed=0.0, t_end=0.0,
               max_steps=0, terms=TERM_ALL, theta_literal=0, record=0, replay=None,
-              nthreads=0):
+              phase=False, nthreads=0):
     """Integrate each inspiral from omega0 to omega_f (Sec. II).
 
     record > 0 keeps up to `record` accepted step sizes per inspiral (for replay).
     replay = dict(h=[n, k], n_t=[n], n_w=[n]) re-runs a recorded step sequence.
+    phase=True also integrates the orbital phase (d Phi/dt = omega, Phi(0) = 0).
     Returns dict(y [10, n], t [n], steps [3, n] int64 (accepted, rejected, RHS
-    evaluations), status [n], n_tw [2, n], and h_record/n_t/n_w when recording).
+    evaluations), status [n], n_tw [2, n], phase [n] when asked for, and
+    h_record/n_t/n_w when recording).
     """
     omega0 = _f64(omega0)
     n = omega0.shape[0]
@@ -118,10 +120,13 @@ def integrate(m, S0, L0, omega0, omega_f, tol, *, h0=0.0, h_fixed=0.0, t_end=0.0
         o.replay_stride = rh.shape[1]; keep += [rh, nt, nw]
     y = np.empty((10, n)); t = np.empty(n); steps = np.empty((3, n), dtype=np.int64)
     status = np.empty(n, dtype=np.int32); ntw = np.empty((2, n), dtype=np.int32)
+    ph = np.empty(n) if phase else None
     lib().oracle_integrate(n, _p(m), _p(S0), _p(L0), _p(omega0), float(omega_f), float(tol),
-                           C.byref(o), _p(y), _p(t), _p(steps), _p(status), _p(ntw),
+                           C.byref(o), _p(y), _p(t), _p(steps), _p(status), _p(ntw), _p(ph),
                            int(nthreads))
     out = {"y": y, "t": t, "steps": steps, "status": status, "n_tw": ntw}
+    if phase:
+        out["phase"] = ph
     if record:
         out["h_record"] = keep[0]
         out["replay"] = {"h": keep[0], "n_t": ntw[0].copy(), "n_w": ntw[1].copy()}

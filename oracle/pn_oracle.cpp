@@ -19,7 +19,13 @@
  *   - the integration of that system from omega0 to omega_f with the
  *     Dormand-Prince method, tolerance tol and initial step h = 10 (Sec. II);
  *   - the unit-vector scalar products S1_hat.S2_hat, S_i_hat.L_hat used to
- *     analyse the final states (Sec. V).
+ *     analyse the final states (Sec. V);
+ *   - on request, the orbital phase Phi(t) = integral of omega dt from 0
+ *     (not a quantity of the paper: an added output for waveform-style use),
+ *     integrated by the same Dormand-Prince steps as a pure quadrature: its
+ *     derivative omega does not depend on Phi, so only the stage values of
+ *     omega enter, and Phi is left out of the error norm, so the step
+ *     sequence is the one without it.
  *
  * Readings taken where the paper is silent or ambiguous (each is repeated in
  * the design notes of the repository):
@@ -291,12 +297,14 @@ struct Mode {
     const double* replay; int n_replay_t, n_replay_w;
     /* record of accepted steps (same layout as replay); NULL when not recording */
     double* record; long long record_cap;
+    bool phase;        /* also integrate the orbital phase */
 };
 
 template <class T>
 struct Result {
     T y[10];
     T t;
+    T phase;           /* integral of omega dt (when requested) */
     long long acc, rej, nrhs;
     int status;
     int n_t, n_w;      /* accepted t-steps and omega-steps */
@@ -321,7 +329,7 @@ Result<T> integrate_one(const T& m1, const T& m2, const T* y0, const Mode& md) {
     using std::sqrt; using std::pow; using std::fabs; using std::isfinite;
     Result<T> r;
     for (int c = 0; c < 10; ++c) r.y[c] = y0[c];
-    r.t = T(0.0); r.acc = r.rej = r.nrhs = 0; r.status = ST_OK; r.n_t = r.n_w = 0;
+    r.t = T(0.0); r.phase = T(0.0); r.acc = r.rej = r.nrhs = 0; r.status = ST_OK; r.n_t = r.n_w = 0;
 
     bool bad = !(val(m1) > 0.0) || !(val(m2) > 0.0) || !(val(y0[0]) > 0.0);
     for (int c = 0; c < 10; ++c) bad = bad || !std::isfinite(val(y0[c]));
@@ -334,10 +342,12 @@ Result<T> integrate_one(const T& m1, const T& m2, const T* y0, const Mode& md) {
     if (!t_end_mode && !(val(y0[0]) < md.omega_f)) { r.status = ST_DONE_AT_START; return r; }
 
     T k[7][10], dtv[7];
+    T kp[7];           /* d Phi / d(variable) = omega dt/d(variable) at each stage */
     T y[10], Y[10], y5[10];
     for (int c = 0; c < 10; ++c) y[c] = y0[c];
     bool omega_mode = false;
     deriv(m1, m2, y, k[0], &dtv[0], omega_mode, md);
+    if (md.phase) kp[0] = y[0] * dtv[0];
     r.nrhs = 1;
 
     T h = T(fixed ? md.h_fixed : (md.h0 > 0.0 ? md.h0 : 10.0));   /* R9 */
@@ -366,6 +376,7 @@ Result<T> integrate_one(const T& m1, const T& m2, const T* y0, const Mode& md) {
                     dtv[0] = inv;
                     for (int c = 1; c < 10; ++c) k[0][c] = k[0][c] * inv;
                     k[0][0] = T(1.0);
+                    if (md.phase) kp[0] = y[0] * inv;
                     continue;
                 }
             }
@@ -397,6 +408,7 @@ Result<T> integrate_one(const T& m1, const T& m2, const T* y0, const Mode& md) {
                 Y[c] = y[c] + htry * acc;
             }
             deriv(m1, m2, Y, k[s], &dtv[s], omega_mode, md);
+            if (md.phase) kp[s] = Y[0] * dtv[s];
             r.nrhs += 1;
         }
         for (int c = 0; c < 10; ++c) y5[c] = Y[c];   /* stage 7 point = 5th-order solution */
@@ -436,6 +448,7 @@ Result<T> integrate_one(const T& m1, const T& m2, const T* y0, const Mode& md) {
                 dtv[0] = inv;
                 for (int c = 1; c < 10; ++c) k[0][c] = k[0][c] * inv;
                 k[0][0] = T(1.0);
+                if (md.phase) kp[0] = y[0] * inv;
                 h = T(md.omega_f) - y[0];
                 last_rejected = false;
                 continue;
@@ -450,6 +463,16 @@ Result<T> integrate_one(const T& m1, const T& m2, const T* y0, const Mode& md) {
                 r.t = r.t + htry * dt;
             } else {
                 r.t = r.t + htry;
+            }
+            if (md.phase) {
+                /* the 5th-order weights applied to d Phi / d(variable) */
+                T dphi = T(0.0);
+                for (int j = 0; j < 7; ++j) {
+                    if (DP_B[j].num == 0) continue;
+                    dphi = dphi + rv(DP_B[j]) * kp[j];
+                }
+                r.phase = r.phase + htry * dphi;
+                kp[0] = kp[6];
             }
             for (int c = 0; c < 10; ++c) y[c] = y5[c];
             if (md.record && replay_pos < md.record_cap) md.record[replay_pos] = val(htry);
@@ -554,6 +577,7 @@ static Mode make_mode(double omega_f, double tol, const oracle_opts* o) {
     md.theta_literal = o ? o->theta_literal : 0;
     md.replay = nullptr; md.n_replay_t = 0; md.n_replay_w = 0;
     md.record = nullptr; md.record_cap = 0;
+    md.phase = false;
     return md;
 }
 
@@ -573,12 +597,14 @@ int oracle_rhs(int64_t n, const double* m, const double* y, double* dydt, int32_
 /* Integrate n inspirals.  m [2][n], S0 [6][n], L0 [3][n], omega0 [n];
  * outputs y_final [10][n], t_final [n], steps [3][n] (accepted, rejected,
  * RHS evaluations), status [n], n_steps_tw [2][n] (accepted t-steps and
- * omega-steps; may be NULL). */
+ * omega-steps; may be NULL), phase [n] (the orbital phase at t_final; may be
+ * NULL, and then it is not integrated). */
 int oracle_integrate(int64_t n, const double* m, const double* S0, const double* L0,
                      const double* omega0, double omega_f, double tol, const oracle_opts* o,
                      double* y_final, double* t_final, int64_t* steps, int32_t* status,
-                     int32_t* n_steps_tw, int32_t nthreads) {
-    const Mode base = make_mode(omega_f, tol, o);
+                     int32_t* n_steps_tw, double* phase, int32_t nthreads) {
+    Mode base = make_mode(omega_f, tol, o);
+    base.phase = phase != nullptr;
     parallel_for(n, nthreads, [&](int64_t i) {
         Mode md = base;
         if (o && o->replay) {
@@ -600,6 +626,7 @@ int oracle_integrate(int64_t n, const double* m, const double* S0, const double*
         steps[i] = r.acc; steps[n + i] = r.rej; steps[2 * n + i] = r.nrhs;
         status[i] = r.status;
         if (n_steps_tw) { n_steps_tw[i] = r.n_t; n_steps_tw[n + i] = r.n_w; }
+        if (phase) phase[i] = r.phase;
     });
     return 0;
 }
