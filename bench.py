@@ -109,6 +109,8 @@ def kernel_resources(kernel: str, block: int):
             "integrate_persistent_f32s": f"integrate_persistent_f32sILi{block}E",
             "integrate_static_f64": f"integrate_static_f64ILi{block}ELb0E",
             "integrate_static_f32s": f"integrate_static_f32sILi{block}E"}.get(kernel)
+    if kernel.endswith("_phase"):
+        want = f"{kernel}ILi{block}E"
     for name, fields in build.resource_usage().items():
         if want and want in name:
             keep = ("VGPRs", "AGPRs", "ScratchSize [bytes/lane]", "Occupancy [waves/SIMD]", "VGPRs Spill",
@@ -317,6 +319,8 @@ def main() -> int:
                     help="throughput against n = 2^8 .. 2^22, replicated and heterogeneous inspirals")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run three plain device copies of 512 MiB (counter calibration)")
+    ap.add_argument("--phase", action="store_true",
+                    help="time pn_integrate_phase (the orbital phase integrated alongside)")
     ap.add_argument("--autotune", action="store_true",
                     help="choose refill threshold and block size with pn_autotune on a 2^20 sample first")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -358,9 +362,10 @@ def main() -> int:
         tuned = {"refill_min": opts.refill_min, "block": opts.block,
                  "table_ms": {f"{r},{b}": v for (r, b), v in table.items()}}
 
+    integrate = api.pn_integrate_phase if args.phase else api.pn_integrate
+
     def step():
-        api.pn_integrate(d["m"], d["S"], d["L"], d["omega0"], pop["omega_f"], pop["tol"], opts,
-                         out=out, stream=stream)
+        integrate(d["m"], d["S"], d["L"], d["omega0"], pop["omega_f"], pop["tol"], opts, out=out, stream=stream)
 
     if args.adjoint:
         return bench_adjoint(args, api, pop, d, w, step, stream)
@@ -394,7 +399,7 @@ def main() -> int:
     peak = FP64_VECTOR_PEAK_TFLOPS if precision == "fp64" else FP32_VECTOR_PEAK_TFLOPS
     n = pop["n"]
     value = n * args.steps / wall
-    kernel = f"integrate_{args.schedule}_{'f64' if precision == 'fp64' else 'f32s'}"
+    kernel = f"integrate_{args.schedule}_{'f64' if precision == 'fp64' else 'f32s'}" + ("_phase" if args.phase else "")
     traffic = measured_traffic(kernel, w.name)
     resources = kernel_resources(kernel, opts.block or 256)
     res = {
@@ -429,8 +434,8 @@ def main() -> int:
     }
     if precision != "fp64":
         # the same population in FP64 (untimed) as the reference for the error report
-        out64 = api.pn_integrate(d["m"], d["S"], d["L"], d["omega0"], pop["omega_f"], pop["tol"],
-                                 api.make_opts(), stream=stream)
+        out64 = integrate(d["m"], d["S"], d["L"], d["omega0"], pop["omega_f"], pop["tol"],
+                          api.make_opts(), stream=stream)
         torch.cuda.synchronize()
         dd = np.abs(out["dots"].cpu().numpy() - out64["dots"].cpu().numpy())
         res["error_vs_fp64"] = {
@@ -438,6 +443,10 @@ def main() -> int:
             "max": dd.max(axis=1).tolist(), "p99": np.percentile(dd, 99, axis=1).tolist(),
             "t_rel_max": float(np.abs(out["t"].cpu().numpy() / out64["t"].cpu().numpy() - 1).max()),
             "reference": "the FP64 GPU path on the whole population (itself within 1e-8 of the oracle)"}
+        if args.phase:
+            pr = np.abs(out["phase"].cpu().numpy() / out64["phase"].cpu().numpy() - 1)
+            res["error_vs_fp64"]["phase_rel_max"] = float(pr.max())
+            res["error_vs_fp64"]["phase_rel_p99"] = float(np.percentile(pr, 99))
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(pop, args.cpu_budget)
     print(json.dumps(res), flush=True)

@@ -136,6 +136,25 @@ int pn_integrate(int64_t n, int64_t ld,
                  double* dots, void* stream);
 
 /*
+ * pn_integrate_phase -- pn_integrate that also integrates the orbital phase
+ * Phi(t) = integral of omega dt from Phi(0) = 0 (a quantity the paper does not
+ * use; the phase of waveform-style outputs).  Each accepted step adds h times
+ * the 5th-order weights applied to the stage values of omega (times
+ * dt/d omega on the final stretch in omega); Phi is left out of the error
+ * norm, so the steps and every other output are bit-identical to
+ * pn_integrate's.  phase [ld]: device float64 output, Phi at t_final (0 for
+ * DONE_AT_START and BAD_INPUT; at the last accepted state for a failure).
+ * In PN_PREC_FP32_SPLIT the per-step increment is formed in FP32 and summed
+ * in FP64, like the state.  Other arguments, errors and layout as
+ * pn_integrate; phase must not be NULL when n > 0.
+ */
+int pn_integrate_phase(int64_t n, int64_t ld,
+                       const double* m, const double* S0, const double* L0, const double* omega0,
+                       double omega_f, double tol, const pn_opts* opt,
+                       double* y_final, double* t_final, int32_t* steps, int32_t* status,
+                       double* dots, double* phase, void* stream);
+
+/*
  * pn_autotune -- choose the launch shape of pn_integrate for a population:
  * times pn_integrate on its first `sample` inspirals (all n when sample <= 0
  * or sample > n) for every candidate refill threshold {2, 3, 4, 6} and block

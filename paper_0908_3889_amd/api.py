@@ -73,6 +73,18 @@ def pn_integrate(m, S0, L0, omega0, omega_f, tol, opts: PnOpts | None = None, ou
     Returns dict(y [10, n], t [n], steps [3, n] int32, status [n] int32,
     dots [3, n] or None).  Asynchronous on the current stream.
     """
+    return _integrate(False, m, S0, L0, omega0, omega_f, tol, opts, out, dots, stream)
+
+
+def pn_integrate_phase(m, S0, L0, omega0, omega_f, tol, opts: PnOpts | None = None, out=None,
+                       dots: bool = True, stream=None) -> dict:
+    """pn_integrate plus the orbital phase Phi = integral of omega dt at
+    t_final: out["phase"] [n] float64.  Every other output is bit-identical
+    to pn_integrate's."""
+    return _integrate(True, m, S0, L0, omega0, omega_f, tol, opts, out, dots, stream)
+
+
+def _integrate(phase, m, S0, L0, omega0, omega_f, tol, opts, out, dots, stream) -> dict:
     n = int(omega0.shape[0])
     _soa(omega0, 1, n, "omega0")
     _soa(m, 2, n, "m"); _soa(S0, 6, n, "S0"); _soa(L0, 3, n, "L0")
@@ -86,15 +98,23 @@ def pn_integrate(m, S0, L0, omega0, omega_f, tol, opts: PnOpts | None = None, ou
     if out.get("dots") is not None:
         _soa(out["dots"], 3, n, "dots")
         lds.add(_ld(out["dots"], n))
+    if phase:
+        if out.get("phase") is None:
+            out["phase"] = torch.empty((n,), dtype=torch.float64, device=omega0.device)
+        _soa(out["phase"], 1, n, "phase")
     if n > 0 and len(lds) != 1:
         raise ValueError("all [components, n] arrays must share one leading dimension")
     ld = lds.pop() if n > 0 else 0
     o = opts if opts is not None else make_opts()
     p = lambda t: C.c_void_p(t.data_ptr()) if t is not None else None
-    rc = load().pn_integrate(n, ld, p(m), p(S0), p(L0), p(omega0), float(omega_f), float(tol),
-                             C.byref(o), p(out["y"]), p(out["t"]), p(out["steps"]),
-                             p(out["status"]), p(out.get("dots")), _stream(stream))
-    check(rc, "pn_integrate")
+    args = (n, ld, p(m), p(S0), p(L0), p(omega0), float(omega_f), float(tol), C.byref(o), p(out["y"]),
+            p(out["t"]), p(out["steps"]), p(out["status"]), p(out.get("dots")))
+    if phase:
+        rc = load().pn_integrate_phase(*args, p(out["phase"]), _stream(stream))
+        check(rc, "pn_integrate_phase")
+    else:
+        rc = load().pn_integrate(*args, _stream(stream))
+        check(rc, "pn_integrate")
     return out
 
 

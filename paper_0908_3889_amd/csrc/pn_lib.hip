@@ -99,16 +99,19 @@ struct Io {
     int32_t* __restrict__ steps;
     int32_t* __restrict__ status;
     double* __restrict__ dots;
+    double* __restrict__ phase;   // orbital phase at t_final, or null
 };
 
 __device__ __forceinline__ bool finite(double v) { return __builtin_isfinite(v); }
 
+template <bool PHASE = false>
 __device__ void write_out(const Io& io, const Uni& u, int64_t i, const double* y, double t, int acc,
-                          int rej, int nrhs, int st) {
+                          int rej, int nrhs, int st, double phase = 0.0) {
     const int64_t ld = u.ld;
 #pragma unroll
     for (int c = 0; c < 10; ++c) io.y[c * ld + i] = y[c];
     io.t[i] = t;
+    if (PHASE) io.phase[i] = phase;
     io.steps[i] = acc;
     io.steps[ld + i] = rej;
     io.steps[2 * ld + i] = nrhs;
@@ -129,6 +132,7 @@ __device__ void write_out(const Io& io, const Uni& u, int64_t i, const double* y
 // Read inspiral idx into y and the masses; returns 0, or the status of an
 // inspiral that is finished at once (bad input, or omega0 >= omega_f), whose
 // outputs are then already written.
+template <bool PHASE = false>
 __device__ int read_input(const Io& io, const Uni& u, int64_t idx, double* y, double& m1, double& m2) {
     const int64_t ld = u.ld;
     m1 = io.m[idx];
@@ -141,9 +145,9 @@ __device__ int read_input(const Io& io, const Uni& u, int64_t idx, double* y, do
     bool bad = !(m1 > 0.0) || !(m2 > 0.0) || !(y[0] > 0.0) || !finite(m1) || !finite(m2);
 #pragma unroll
     for (int c = 0; c < 10; ++c) bad = bad || !finite(y[c]);
-    if (bad) { write_out(io, u, idx, y, 0.0, 0, 0, 0, PN_ST_BAD_INPUT); return PN_ST_BAD_INPUT; }
+    if (bad) { write_out<PHASE>(io, u, idx, y, 0.0, 0, 0, 0, PN_ST_BAD_INPUT); return PN_ST_BAD_INPUT; }
     if (!u.tend && !(y[0] < u.omega_f)) {
-        write_out(io, u, idx, y, 0.0, 0, 0, 0, PN_ST_DONE_AT_START);
+        write_out<PHASE>(io, u, idx, y, 0.0, 0, 0, 0, PN_ST_DONE_AT_START);
         return PN_ST_DONE_AT_START;
     }
     return 0;
@@ -271,6 +275,7 @@ struct LaneF64 {
     double lnv;       // ln|M omega| at y, carried from the stage that produced y
     double dt1;       // dt/d(variable) of k1: 1 in time mode, 1/omega-dot in omega mode
     double t, h;
+    double phase;     // integral of omega dt (phase kernels only)
     Row row;
     int64_t idx;
     int acc, rej, nrhs;
@@ -278,19 +283,23 @@ struct LaneF64 {
     bool omega_mode, last_rej;
 };
 
-template <bool RECORD>
+// PHASE: also integrate the orbital phase, d Phi/dt = omega, as a quadrature
+// on the same steps (5th-order weights on the stage values of omega times
+// dt/d(variable)), outside the error norm, so the steps are unchanged.
+template <bool RECORD, bool PHASE = false>
 struct F64 {
     using LaneT = LaneF64;
 
     static __device__ int load(const Io& io, const Uni& u, LaneT& L, int64_t idx) {
         L.idx = idx;
         double m1, m2;
-        const int st = read_input(io, u, idx, L.y, m1, m2);
+        const int st = read_input<PHASE>(io, u, idx, L.y, m1, m2);
         if (st) return st;
         L.t = 0.0;
         L.acc = 0; L.rej = 0;
         L.omega_mode = false; L.last_rej = false;
         L.h = u.fixed ? u.h_fixed : u.h0;
+        L.phase = 0.0;
         make_row(L.row, m1, m2, u.terms, u.theta_literal);
         LogBase lb;
         L.lnv = rhs<Row, false>(L.row, u.tc, lb, L.y, L.k1);
@@ -302,7 +311,7 @@ struct F64 {
     }
 
     static __device__ void finish(const Io& io, const Uni& u, const LaneT& L, int st) {
-        write_out(io, u, L.idx, L.y, L.t, L.acc, L.rej, L.nrhs, st);
+        write_out<PHASE>(io, u, L.idx, L.y, L.t, L.acc, L.rej, L.nrhs, st, L.phase);
         if (RECORD) {
             double* tp = tape_of(u, L.idx);
             const int nt = L.omega_mode ? L.nt : L.acc;
@@ -328,6 +337,8 @@ struct F64 {
         double Y[10], k2[10], k3[10], k4[10], k5[10], k6[10];
         double dtj;
         double dts = B1 * L.dt1;     // sum_j b_j dt_j, used in omega mode only
+        double ps = 0.0;             // sum_j b_j omega_j dt_j (PHASE)
+        if (PHASE) ps = B1 * (y[0] * L.dt1);
         LogBase lb;
         lb.w = y[0];
         lb.iw = rcp_pos(y[0]);
@@ -346,6 +357,7 @@ struct F64 {
             for (int c = 0; c < 10; ++c) Y[c] = __builtin_fma(c2, k2[c], __builtin_fma(c1, k1[c], y[c]));
             rhs<Row, true>(R, u.tc, lb, Y, k3);
             if (any_w) { to_omega_variable(k3, dtj, L.omega_mode); dts = __builtin_fma(B3, dtj, dts); }
+            if (PHASE) ps = __builtin_fma(B3, Y[0] * (any_w ? dtj : 1.0), ps);
         }
         {
             const double c1 = h * A41, c2 = h * A42, c3 = h * A43;
@@ -354,6 +366,7 @@ struct F64 {
                 Y[c] = __builtin_fma(c3, k3[c], __builtin_fma(c2, k2[c], __builtin_fma(c1, k1[c], y[c])));
             rhs<Row, true>(R, u.tc, lb, Y, k4);
             if (any_w) { to_omega_variable(k4, dtj, L.omega_mode); dts = __builtin_fma(B4, dtj, dts); }
+            if (PHASE) ps = __builtin_fma(B4, Y[0] * (any_w ? dtj : 1.0), ps);
         }
         {
             const double c1 = h * A51, c2 = h * A52, c3 = h * A53, c4 = h * A54;
@@ -363,6 +376,7 @@ struct F64 {
                        __builtin_fma(c2, k2[c], __builtin_fma(c1, k1[c], y[c]))));
             rhs<Row, true>(R, u.tc, lb, Y, k5);
             if (any_w) { to_omega_variable(k5, dtj, L.omega_mode); dts = __builtin_fma(B5, dtj, dts); }
+            if (PHASE) ps = __builtin_fma(B5, Y[0] * (any_w ? dtj : 1.0), ps);
         }
         {
             const double c1 = h * A61, c2 = h * A62, c3 = h * A63, c4 = h * A64, c5 = h * A65;
@@ -372,6 +386,7 @@ struct F64 {
                        __builtin_fma(c2, k2[c], __builtin_fma(c1, k1[c], y[c])))));
             rhs<Row, true>(R, u.tc, lb, Y, k6);
             if (any_w) { to_omega_variable(k6, dtj, L.omega_mode); dts = __builtin_fma(B6, dtj, dts); }
+            if (PHASE) ps = __builtin_fma(B6, Y[0] * (any_w ? dtj : 1.0), ps);
         }
         // stage 7 point = 5th-order solution; the error sum over k1, k3..k6 is
         // formed now so that those vectors die before the last RHS
@@ -403,6 +418,7 @@ struct F64 {
         const int acc0 = L.acc;
         const int r = control<RECORD>(u, L, go, st0, fin, z, h, last, Y, k7, dt7, dts);
         L.lnv = L.acc != acc0 ? lnv7 : L.lnv;
+        if (PHASE) L.phase = L.acc != acc0 ? __builtin_fma(h, ps, L.phase) : L.phase;
         return r;
     }
 };
@@ -415,6 +431,7 @@ struct LaneF32 {
     float k1[10];     // FSAL derivative, FP32
     float dt1;
     double t, h;
+    double phase;     // integral of omega dt, FP64 sum of FP32 increments (phase kernels only)
     RowF row;
     int64_t idx;
     int acc, rej, nrhs;
@@ -422,18 +439,20 @@ struct LaneF32 {
     bool omega_mode, last_rej;
 };
 
+template <bool PHASE = false>
 struct F32Split {
     using LaneT = LaneF32;
 
     static __device__ int load(const Io& io, const Uni& u, LaneT& L, int64_t idx) {
         L.idx = idx;
         double m1, m2;
-        const int st = read_input(io, u, idx, L.y, m1, m2);
+        const int st = read_input<PHASE>(io, u, idx, L.y, m1, m2);
         if (st) return st;
         L.t = 0.0;
         L.acc = 0; L.rej = 0;
         L.omega_mode = false; L.last_rej = false;
         L.h = u.fixed ? u.h_fixed : u.h0;
+        L.phase = 0.0;
         Row r;
         make_row(r, m1, m2, u.terms, u.theta_literal);
         L.row = to_f32(r);
@@ -447,7 +466,7 @@ struct F32Split {
     }
 
     static __device__ void finish(const Io& io, const Uni& u, const LaneT& L, int st) {
-        write_out(io, u, L.idx, L.y, L.t, L.acc, L.rej, L.nrhs, st);
+        write_out<PHASE>(io, u, L.idx, L.y, L.t, L.acc, L.rej, L.nrhs, st, L.phase);
     }
 
     // One attempted step, run by every lane as in the FP64 lane.
@@ -467,6 +486,8 @@ struct F32Split {
         for (int c = 0; c < 10; ++c) yf[c] = (float)L.y[c];
         float dtj;
         float dts = (float)B1 * L.dt1;
+        float ps = 0.0f;
+        if (PHASE) ps = (float)B1 * (yf[0] * L.dt1);
         {
             const float c1 = hf * (float)A21;
 #pragma unroll
@@ -480,6 +501,7 @@ struct F32Split {
             for (int c = 0; c < 10; ++c) Y[c] = __builtin_fmaf(c2, k2[c], __builtin_fmaf(c1, k1[c], yf[c]));
             rhs_f32(R, u.tcf, Y, k3);
             if (any_w) { to_omega_variable(k3, dtj, L.omega_mode); dts = __builtin_fmaf((float)B3, dtj, dts); }
+            if (PHASE) ps = __builtin_fmaf((float)B3, Y[0] * (any_w ? dtj : 1.0f), ps);
         }
         {
             const float c1 = hf * (float)A41, c2 = hf * (float)A42, c3 = hf * (float)A43;
@@ -488,6 +510,7 @@ struct F32Split {
                 Y[c] = __builtin_fmaf(c3, k3[c], __builtin_fmaf(c2, k2[c], __builtin_fmaf(c1, k1[c], yf[c])));
             rhs_f32(R, u.tcf, Y, k4);
             if (any_w) { to_omega_variable(k4, dtj, L.omega_mode); dts = __builtin_fmaf((float)B4, dtj, dts); }
+            if (PHASE) ps = __builtin_fmaf((float)B4, Y[0] * (any_w ? dtj : 1.0f), ps);
         }
         {
             const float c1 = hf * (float)A51, c2 = hf * (float)A52, c3 = hf * (float)A53, c4 = hf * (float)A54;
@@ -497,6 +520,7 @@ struct F32Split {
                        __builtin_fmaf(c2, k2[c], __builtin_fmaf(c1, k1[c], yf[c]))));
             rhs_f32(R, u.tcf, Y, k5);
             if (any_w) { to_omega_variable(k5, dtj, L.omega_mode); dts = __builtin_fmaf((float)B5, dtj, dts); }
+            if (PHASE) ps = __builtin_fmaf((float)B5, Y[0] * (any_w ? dtj : 1.0f), ps);
         }
         {
             const float c1 = hf * (float)A61, c2 = hf * (float)A62, c3 = hf * (float)A63, c4 = hf * (float)A64,
@@ -507,6 +531,7 @@ struct F32Split {
                        __builtin_fmaf(c2, k2[c], __builtin_fmaf(c1, k1[c], yf[c])))));
             rhs_f32(R, u.tcf, Y, k6);
             if (any_w) { to_omega_variable(k6, dtj, L.omega_mode); dts = __builtin_fmaf((float)B6, dtj, dts); }
+            if (PHASE) ps = __builtin_fmaf((float)B6, Y[0] * (any_w ? dtj : 1.0f), ps);
         }
         // 5th-order increment D (FP32), the stage-7 point, and the error sum
         float D[10], Ep[10];
@@ -534,7 +559,11 @@ struct F32Split {
         bool fin = u.fixed || !__builtin_isnan(z);
 #pragma unroll
         for (int c = 0; c < 10; ++c) fin = fin && finite(ynew[c]) && __builtin_isfinite(k7[c]);
-        return control<false>(u, L, go, st0, fin, z, h, last, ynew, k7, dt7, dts);
+        const int acc0 = L.acc;
+        const int r = control<false>(u, L, go, st0, fin, z, h, last, ynew, k7, dt7, dts);
+        // the FP32 increment is summed in FP64, as the state is
+        if (PHASE) L.phase = L.acc != acc0 ? __builtin_fma(h, (double)ps, L.phase) : L.phase;
+        return r;
     }
 };
 
@@ -624,7 +653,20 @@ void integrate_persistent_f64(Io io, Uni u, unsigned long long* counter) {
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(PN_WPE_F32)))
 void integrate_persistent_f32s(Io io, Uni u, unsigned long long* counter) {
-    persistent_loop<F32Split>(io, u, counter);
+    persistent_loop<F32Split<>>(io, u, counter);
+}
+
+// the same loops with the orbital phase integrated alongside
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(PN_WPE_F64)))
+void integrate_persistent_f64_phase(Io io, Uni u, unsigned long long* counter) {
+    persistent_loop<F64<false, true>>(io, u, counter);
+}
+
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(PN_WPE_F32)))
+void integrate_persistent_f32s_phase(Io io, Uni u, unsigned long long* counter) {
+    persistent_loop<F32Split<true>>(io, u, counter);
 }
 
 template <int BLOCK, bool RECORD>
@@ -636,7 +678,19 @@ void integrate_static_f64(Io io, Uni u) {
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(PN_WPE_F32)))
 void integrate_static_f32s(Io io, Uni u) {
-    static_loop<F32Split>(io, u, (int64_t)blockIdx.x * BLOCK + threadIdx.x);
+    static_loop<F32Split<>>(io, u, (int64_t)blockIdx.x * BLOCK + threadIdx.x);
+}
+
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(PN_WPE_F64)))
+void integrate_static_f64_phase(Io io, Uni u) {
+    static_loop<F64<false, true>>(io, u, (int64_t)blockIdx.x * BLOCK + threadIdx.x);
+}
+
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(PN_WPE_F32)))
+void integrate_static_f32s_phase(Io io, Uni u) {
+    static_loop<F32Split<true>>(io, u, (int64_t)blockIdx.x * BLOCK + threadIdx.x);
 }
 
 // ===========================================================================
@@ -1030,9 +1084,12 @@ template <int BLOCK>
 hipError_t launch_forward(const Io& io, const Uni& u, int precision, int schedule, int waves_per_simd, int cus,
                           unsigned long long* counter, hipStream_t s) {
     const bool f32 = precision == PN_PREC_FP32_SPLIT;
+    const bool ph = io.phase != nullptr;
     if (schedule == PN_SCHED_STATIC) {
         const int64_t grid = (u.n + BLOCK - 1) / BLOCK;
-        if (f32) hipLaunchKernelGGL(integrate_static_f32s<BLOCK>, dim3((unsigned)grid), dim3(BLOCK), 0, s, io, u);
+        if (ph && f32) hipLaunchKernelGGL(integrate_static_f32s_phase<BLOCK>, dim3((unsigned)grid), dim3(BLOCK), 0, s, io, u);
+        else if (ph) hipLaunchKernelGGL(integrate_static_f64_phase<BLOCK>, dim3((unsigned)grid), dim3(BLOCK), 0, s, io, u);
+        else if (f32) hipLaunchKernelGGL(integrate_static_f32s<BLOCK>, dim3((unsigned)grid), dim3(BLOCK), 0, s, io, u);
         else if (u.tape) hipLaunchKernelGGL((integrate_static_f64<BLOCK, true>), dim3((unsigned)grid), dim3(BLOCK), 0, s, io, u);
         else hipLaunchKernelGGL((integrate_static_f64<BLOCK, false>), dim3((unsigned)grid), dim3(BLOCK), 0, s, io, u);
         return hipGetLastError();
@@ -1044,7 +1101,11 @@ hipError_t launch_forward(const Io& io, const Uni& u, int precision, int schedul
     int64_t waves = (int64_t)cus * 4 * waves_per_simd;
     if (waves > waves_needed) waves = waves_needed;
     const int64_t grid = (waves * 64 + BLOCK - 1) / BLOCK;
-    if (f32)
+    if (ph && f32)
+        hipLaunchKernelGGL(integrate_persistent_f32s_phase<BLOCK>, dim3((unsigned)grid), dim3(BLOCK), 0, s, io, u, counter);
+    else if (ph)
+        hipLaunchKernelGGL(integrate_persistent_f64_phase<BLOCK>, dim3((unsigned)grid), dim3(BLOCK), 0, s, io, u, counter);
+    else if (f32)
         hipLaunchKernelGGL(integrate_persistent_f32s<BLOCK>, dim3((unsigned)grid), dim3(BLOCK), 0, s, io, u, counter);
     else if (u.tape)
         hipLaunchKernelGGL((integrate_persistent_f64<BLOCK, true>), dim3((unsigned)grid), dim3(BLOCK), 0, s, io, u, counter);
@@ -1080,7 +1141,7 @@ const char* pn_version(void) { return "pn-gfx950 0.2"; }
 static int integrate_impl(int64_t n, int64_t ld, const double* m, const double* S0, const double* L0,
                           const double* omega0, double omega_f, double tol, const pn_opts* opt,
                           double* y_final, double* t_final, int32_t* steps, int32_t* status, double* dots,
-                          double* tape, int64_t cap_steps, int32_t ckpt_every, void* stream) {
+                          double* tape, int64_t cap_steps, int32_t ckpt_every, double* phase, void* stream) {
     pn_opts o;
     std::memset(&o, 0, sizeof(o));
     if (opt) o = *opt;
@@ -1141,6 +1202,7 @@ static int integrate_impl(int64_t n, int64_t ld, const double* m, const double* 
     Io io;
     io.m = m; io.S0 = S0; io.L0 = L0; io.w0 = omega0;
     io.y = y_final; io.t = t_final; io.steps = steps; io.status = status; io.dots = dots;
+    io.phase = phase;
 
     unsigned long long* counter = ctx->counters + (ctx->next.fetch_add(1) % kCounterSlots);
     hipStream_t s = (hipStream_t)stream;
@@ -1159,7 +1221,16 @@ int pn_integrate(int64_t n, int64_t ld, const double* m, const double* S0, const
                  double* y_final, double* t_final, int32_t* steps, int32_t* status, double* dots,
                  void* stream) {
     return integrate_impl(n, ld, m, S0, L0, omega0, omega_f, tol, opt, y_final, t_final, steps, status, dots,
-                          nullptr, 0, 0, stream);
+                          nullptr, 0, 0, nullptr, stream);
+}
+
+int pn_integrate_phase(int64_t n, int64_t ld, const double* m, const double* S0, const double* L0,
+                       const double* omega0, double omega_f, double tol, const pn_opts* opt,
+                       double* y_final, double* t_final, int32_t* steps, int32_t* status, double* dots,
+                       double* phase, void* stream) {
+    if (n > 0 && !phase) return PN_EINVAL;
+    return integrate_impl(n, ld, m, S0, L0, omega0, omega_f, tol, opt, y_final, t_final, steps, status, dots,
+                          nullptr, 0, 0, phase, stream);
 }
 
 int pn_autotune(int64_t n, int64_t ld, const double* m, const double* S0, const double* L0,
@@ -1221,7 +1292,7 @@ int pn_integrate_record(int64_t n, int64_t ld, const double* m, const double* S0
                         double* tape, int64_t cap_steps, int32_t ckpt_every, void* stream) {
     if (n > 0 && !tape) return PN_EINVAL;
     return integrate_impl(n, ld, m, S0, L0, omega0, omega_f, tol, opt, y_final, t_final, steps, status, dots,
-                          tape, cap_steps, ckpt_every, stream);
+                          tape, cap_steps, ckpt_every, nullptr, stream);
 }
 
 size_t pn_adjoint_workspace_bytes(int64_t n, int32_t ckpt_every) {

@@ -77,6 +77,12 @@ def test_invalid_arguments_return_einval_without_a_device(lib):
     bad = PnOpts(); bad.precision = 2
     assert call(10, 10, opt=bad) == PN_EINVAL
     assert call(0, 0) == PN_OK                       # empty batch: nothing to do
+    ph = lambda n, ld, out, tol=1e-8: lib.pn_integrate_phase(
+        n, ld, fake, fake, fake, fake, 0.05, tol, C.byref(o), fake, fake, fake, fake, z, out, z)
+    assert ph(10, 10, z) == PN_EINVAL                # the phase output is required
+    assert ph(10, 10, fake, tol=-1.0) == PN_EINVAL
+    assert ph(10, 5, fake) == PN_EINVAL
+    assert ph(0, 0, z) == PN_OK
     assert lib.pn_rhs(-1, 0, fake, fake, fake, None, z) == PN_EINVAL
     assert lib.pn_observables(5, 4, fake, fake, z) == PN_EINVAL
     assert lib.pn_observables(0, 0, fake, fake, z) == PN_OK
