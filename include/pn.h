@@ -15,7 +15,8 @@
  *
  * Conventions for every entry point:
  *  - Arrays are structure-of-arrays of float64 (int32 where stated): component
- *    c of inspiral i lives at p[c*ld + i], with leading dimension ld >= n.
+ *    c of inspiral i lives at p[c*ld + i], with leading dimension ld >= n;
+ *    0 <= n <= ld <= PN_MAX_N.
  *  - Every array pointer is a DEVICE pointer on the current HIP device,
  *    allocated and owned by the caller; the library never frees it.  Inputs
  *    are read only; outputs are written for every i < n.
@@ -42,6 +43,10 @@
 #ifdef __cplusplus
 extern "C" {
 #endif
+
+/* Largest n (and leading dimension) any entry point accepts: 2^36 inspirals,
+ * far beyond one GPU's memory; larger values give PN_EINVAL. */
+#define PN_MAX_N ((int64_t)1 << 36)
 
 /* ---- return codes ---------------------------------------------------- */
 #define PN_OK        0

@@ -111,7 +111,7 @@ using namespace pn;
 
 extern "C" int pn_generate(int64_t n, int64_t ld, int64_t first, const pn_gen_spec* spec, double* m, double* S0,
                            double* L0, double* omega0, void* stream) {
-    if (n < 0 || ld < n || first < 0 || !spec) return PN_EINVAL;
+    if (n < 0 || ld < n || ld > PN_MAX_N || first < 0 || first > INT64_MAX - n || !spec) return PN_EINVAL;
     const pn_gen_spec& s = *spec;
     if (bad_range(s.q_lo, s.q_hi) || !(s.q_lo > 0.0) || bad_range(s.chi1_lo, s.chi1_hi) ||
         bad_range(s.chi2_lo, s.chi2_hi) || s.chi1_lo < 0.0 || s.chi1_hi > 1.0 || s.chi2_lo < 0.0 ||

@@ -1145,7 +1145,7 @@ static int integrate_impl(int64_t n, int64_t ld, const double* m, const double* 
     pn_opts o;
     std::memset(&o, 0, sizeof(o));
     if (opt) o = *opt;
-    if (n < 0 || ld < n) return PN_EINVAL;
+    if (n < 0 || ld < n || ld > PN_MAX_N) return PN_EINVAL;
     if (n > 0 && (!m || !S0 || !L0 || !omega0 || !y_final || !t_final || !steps || !status)) return PN_EINVAL;
     const bool fixed = o.h_fixed > 0.0;
     const bool tend = o.t_end > 0.0;
@@ -1237,7 +1237,7 @@ int pn_autotune(int64_t n, int64_t ld, const double* m, const double* S0, const 
                 const double* omega0, double omega_f, double tol, const pn_opts* opt, int64_t sample,
                 int32_t reps, double* y_final, double* t_final, int32_t* steps, int32_t* status,
                 double* dots, pn_opts* best, double* times_ms, void* stream) {
-    if (!best || n < 0 || ld < n) return PN_EINVAL;
+    if (!best || n < 0 || ld < n || ld > PN_MAX_N) return PN_EINVAL;
     pn_opts base;
     std::memset(&base, 0, sizeof(base));
     if (opt) base = *opt;
@@ -1296,7 +1296,7 @@ int pn_integrate_record(int64_t n, int64_t ld, const double* m, const double* S0
 }
 
 size_t pn_adjoint_workspace_bytes(int64_t n, int32_t ckpt_every) {
-    if (n < 0 || ckpt_every < 1) return 0;
+    if (n < 0 || n > PN_MAX_N || ckpt_every < 1) return 0;
     // the replayed states of one segment per inspiral, plus the stage points
     // when those are not kept in LDS
     return (size_t)n * ((size_t)ckpt_every * 11 + (PN_ADJ_Y_LDS ? 0 : 60)) * sizeof(double);
@@ -1307,7 +1307,7 @@ int pn_integrate_adjoint(int64_t n, int64_t ld, const double* m, double omega_f,
                          const double* gy_final, const double* gt_final, double* g_m, double* g_S0,
                          double* g_L0, double* g_omega0, double* workspace, size_t ws_bytes,
                          const int32_t* order, void* stream) {
-    if (n < 0 || ld < n) return PN_EINVAL;
+    if (n < 0 || ld < n || ld > PN_MAX_N) return PN_EINVAL;
     if (cap_steps < 1 || cap_steps > (1 << 28) || ckpt_every < 1 || ckpt_every > 4096) return PN_EINVAL;
     if (n > 0 && (!m || !tape || !status || !gy_final || !g_m || !g_S0 || !g_L0 || !g_omega0 || !workspace))
         return PN_EINVAL;
@@ -1344,7 +1344,7 @@ int pn_integrate_adjoint(int64_t n, int64_t ld, const double* m, double omega_f,
 
 int pn_rhs(int64_t n, int64_t ld, const double* m, const double* y, double* dydt, const pn_opts* opt,
            void* stream) {
-    if (n < 0 || ld < n) return PN_EINVAL;
+    if (n < 0 || ld < n || ld > PN_MAX_N) return PN_EINVAL;
     if (n > 0 && (!m || !y || !dydt)) return PN_EINVAL;
     const int terms = (opt && opt->terms > 0) ? opt->terms : PN_TERM_ALL;
     const int lit = opt ? opt->theta_literal : 0;
@@ -1360,7 +1360,7 @@ int pn_rhs(int64_t n, int64_t ld, const double* m, const double* y, double* dydt
 }
 
 int pn_observables(int64_t n, int64_t ld, const double* y, double* dots, void* stream) {
-    if (n < 0 || ld < n) return PN_EINVAL;
+    if (n < 0 || ld < n || ld > PN_MAX_N) return PN_EINVAL;
     if (n > 0 && (!y || !dots)) return PN_EINVAL;
     if (n == 0) return PN_OK;
     DevCtx* ctx = nullptr;

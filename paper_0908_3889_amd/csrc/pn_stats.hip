@@ -313,7 +313,7 @@ __global__ void fill_nan(double* p, int count) {
 int launched() { return hipGetLastError() == hipSuccess ? PN_OK : PN_EHIP; }
 
 bool bad_common(int64_t n, int64_t ld, int32_t ncomp) {
-    return n < 0 || ld < n || ncomp < 1 || ncomp > kMaxComp;
+    return n < 0 || ld < n || ld > PN_MAX_N || ncomp < 1 || ncomp > kMaxComp;
 }
 
 unsigned blocks_for(int64_t n) {
@@ -371,7 +371,7 @@ int pn_histogram2d(int64_t n, int64_t ld, const double* x, const double* y, int3
 }
 
 size_t pn_stats_workspace_bytes(int64_t n, int32_t ncomp, int32_t ngrid) {
-    if (n < 0 || ncomp < 1 || ncomp > kMaxComp || ngrid < 0) return 0;
+    if (n < 0 || n > PN_MAX_N || ncomp < 1 || ncomp > kMaxComp || ngrid < 0) return 0;
     const size_t pearson = ((size_t)ncomp * kPart * 3 + (size_t)ncomp * 2) * sizeof(double);
     const size_t kde = (size_t)ncomp * kPart * (size_t)ngrid * sizeof(double);
     return pearson > kde ? pearson : kde;
@@ -423,7 +423,7 @@ int pn_kde(int64_t n, int64_t ld, const double* x, int32_t ncomp, const double* 
 }
 
 size_t pn_ks_workspace_bytes(int64_t n) {
-    if (n < 0) return 0;
+    if (n < 0 || n > PN_MAX_N) return 0;
     const size_t tmp = radix_temp_bytes(n);
     if (n > 0 && tmp == 0) return 0;
     // sorted copy, sort scratch (256-byte aligned), partial maxima

@@ -83,6 +83,11 @@ def test_invalid_arguments_return_einval_without_a_device(lib):
     assert ph(10, 10, fake, tol=-1.0) == PN_EINVAL
     assert ph(10, 5, fake) == PN_EINVAL
     assert ph(0, 0, z) == PN_OK
+    big = 1 << 36                                    # PN_MAX_N
+    assert call(big + 1, big + 1) == PN_EINVAL
+    assert call(10, big + 1) == PN_EINVAL
+    assert lib.pn_adjoint_workspace_bytes(big + 1, 16) == 0
+    assert lib.pn_ks_workspace_bytes(big + 1) == 0
     assert lib.pn_rhs(-1, 0, fake, fake, fake, None, z) == PN_EINVAL
     assert lib.pn_observables(5, 4, fake, fake, z) == PN_EINVAL
     assert lib.pn_observables(0, 0, fake, fake, z) == PN_OK
