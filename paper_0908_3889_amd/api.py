@@ -19,9 +19,17 @@ SCHEDULES = {"persistent": _lib.PN_SCHED_PERSISTENT, "static": _lib.PN_SCHED_STA
 PRECISIONS = {"fp64": _lib.PN_PREC_FP64, "fp32split": _lib.PN_PREC_FP32_SPLIT}
 
 
+def _on_current_device(t: torch.Tensor, name: str) -> None:
+    # the library works on the current HIP device
+    if t.device.index is not None and t.device.index != torch.cuda.current_device():
+        raise ValueError(f"{name} is on {t.device}, but the current device is "
+                         f"cuda:{torch.cuda.current_device()} (use torch.cuda.set_device)")
+
+
 def _soa(t: torch.Tensor, comps: int, n: int, name: str, dtype=torch.float64) -> torch.Tensor:
     if not isinstance(t, torch.Tensor) or not t.is_cuda:
         raise TypeError(f"{name} must be a torch tensor on the GPU")
+    _on_current_device(t, name)
     if t.dtype != dtype:
         raise TypeError(f"{name} must be {dtype}")
     if comps == 1:
@@ -284,6 +292,7 @@ def _comp(x, name):
     """A [ncomp, n] float64 device array with unit stride along n."""
     if not isinstance(x, torch.Tensor) or not x.is_cuda:
         raise TypeError(f"{name} must be a torch tensor on the GPU")
+    _on_current_device(x, name)
     if x.dim() == 1:
         x = x.unsqueeze(0)
     if x.dtype != torch.float64 or x.dim() != 2 or (x.shape[1] > 1 and x.stride(1) != 1):
