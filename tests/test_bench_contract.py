@@ -1,0 +1,77 @@
+"""bench.py's output contract: the JSON line's fields, the CPU baseline leg,
+the HBM-traffic lookup, and the refusal of more than one GPU."""
+import json
+import os
+import subprocess
+import sys
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+from paper_0908_3889_amd import population as P  # noqa: E402
+
+REQUIRED = {"metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step", "higher_is_better", "scaling",
+            "vs_baseline", "dtype", "data", "config", "roofline"}
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, cwd=ROOT, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout == ""
+
+
+def test_cpu_baseline_fields():
+    pop = P.generate("equal_mass_maxspin_1k", 64)
+    cb = bench.cpu_baseline(pop, budget_s=0.1)
+    assert cb["kind"] == "oracle" and cb["unit"] == "inspirals/s"
+    assert cb["value"] > 0 and cb["cores"] == len(os.sched_getaffinity(0))
+    assert cb["sample"].startswith("first ") and "of 64 inspirals of equal_mass_maxspin_1k" in cb["sample"]
+    assert cb["rhs_evals_per_s"] > cb["value"]
+
+
+def test_algorithmic_flops_from_step_counts():
+    steps = np.array([[10, 20], [2, 0], [1 + 6 * 12, 1 + 6 * 20]], dtype=np.int32)
+    attempted = np.array([12, 20])
+    want = (steps[2].astype(np.int64) * bench.F_RHS).sum() + (attempted * bench.F_STEP_COMB).sum()
+    assert bench.algorithmic_flops(steps) == float(want)
+
+
+def test_traffic_is_read_only_for_the_current_sources(tmp_path, monkeypatch):
+    from paper_0908_3889_amd import build
+    monkeypatch.setattr(bench, "PROFILES", str(tmp_path))
+    assert bench.measured_traffic("integrate_persistent_f64", "q1to4_1M") is None     # no summary
+    f = tmp_path / "hbm_integrate_persistent_f64_q1to4_1M.txt"
+    f.write_text(f"# x\nhbm_bytes_per_launch: 123456\nsource_digest: {build.source_digest()}\n")
+    assert bench.measured_traffic("integrate_persistent_f64", "q1to4_1M") == 123456.0
+    f.write_text("# x\nhbm_bytes_per_launch: 123456\nsource_digest: 0000\n")
+    assert bench.measured_traffic("integrate_persistent_f64", "q1to4_1M") is None     # stale
+
+
+@pytest.mark.gpu
+def test_bench_line_on_the_gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    r = subprocess.run([sys.executable, "-u", os.path.join(ROOT, "bench.py"), "--workload", "equal_mass_maxspin_1k",
+                        "--steps", "2", "--warmup", "1", "--no-cpu-baseline"], capture_output=True, text=True,
+                       cwd=ROOT, timeout=300)
+    assert r.returncode == 0, r.stderr[-2000:]
+    lines = [ln for ln in r.stdout.splitlines() if ln.strip()]
+    assert len(lines) == 1
+    res = json.loads(lines[0])
+    assert REQUIRED <= set(res)
+    assert res["n_gpus"] == 1 and res["steps"] == 2 and res["warmup"] == 1
+    assert res["value"] > 0 and res["ms_per_step"] > 0 and res["higher_is_better"] is True
+    assert res["vs_baseline"] is None and res["data"] == "synthetic" and res["dtype"] == "f64"
+    assert res["config"]["workload"] == "equal_mass_maxspin_1k" and res["config"]["n"] == 1024
+    rf = res["roofline"]
+    assert rf["bound"] == "alu" and rf["unit"] == "TFLOP/s" and rf["peak"] == 78.6
+    assert 0 < rf["frac"] < 1 and abs(rf["frac"] - rf["achieved"] / rf["peak"]) < 1e-12
+    assert res["kernel"] == "integrate_persistent_f64"
+    assert res["accepted_steps"] > 0 and res["kernel_ms"] > 0
