@@ -189,3 +189,72 @@ def test_autograd_function_loss_of_the_differentiation_workload():
     f = lambda yy: float(((yy[1:4] * yy[4:7]).sum(0) + yy[9])[i])
     fd = (f(lp) - f(lm)) / (2 * eps)
     assert abs(fd - float(S.grad[2, i])) < 1e-2 * max(1.0, abs(fd))
+
+
+def test_record_is_the_same_under_every_launch_shape():
+    """The tape (steps and checkpoints) and the gradient do not depend on the
+    schedule or the block size of the recording launch."""
+    n = 333
+    pop = P.generate("batching_4M", n)
+    gy = np.random.default_rng(4).normal(size=(10, n))
+    K, cap = 16, 4096
+    base_d, base = _record(pop, K=K, cap=cap)
+    gb = _adjoint(base_d, pop, base, gy, None)
+
+    def written(tape):
+        # the counts, the N accepted step sizes and checkpoints 0 .. N // K
+        # (the rest of each row is never written)
+        out = []
+        for row in tape:
+            N = int(row[0] + row[1])
+            out.append(np.concatenate([row[:2 + N], row[2 + cap:2 + cap + 10 * (N // K + 1)]]))
+        return out
+
+    wb = written(base["tape"].cpu().numpy())
+    for kw in (dict(schedule="static"), dict(block=64, refill_min=1), dict(block=512)):
+        d, rec = _record(pop, K=K, cap=cap, **kw)
+        for a, b in zip(written(rec["tape"].cpu().numpy()), wb):
+            np.testing.assert_array_equal(a, b, err_msg=str(kw))
+        g = _adjoint(d, pop, rec, gy, None)
+        for k in ("m", "S0", "L0", "omega0"):
+            np.testing.assert_array_equal(g[k], gb[k], err_msg=f"{kw} {k}")
+
+
+@pytest.mark.parametrize("K", [16, 64, 256])
+def test_full_size_adjoint_samples(K):
+    """The whole 65,536-inspiral differentiation workload in the benchmark's
+    launch configuration (tape cap 1024, lanes ordered by step count, the
+    gradient of sum S1.S2 + sum L_hat_z), checked on 64 sampled inspirals
+    against the oracle's tangent of the GPU's own step sequence."""
+    from paper_0908_3889_amd import api
+    pop = P.generate("adjoint_64k")
+    n = pop["omega0"].size
+    d = api.to_device(pop)
+    rec = api.pn_integrate_record(d["m"], d["S"], d["L"], d["omega0"], pop["omega_f"], pop["tol"],
+                                  cap_steps=1024, ckpt_every=K)
+    y = rec["y"]
+    gy = torch.zeros_like(y)
+    gy[1:4] = y[4:7]
+    gy[4:7] = y[1:4]
+    gy[9] = 1.0
+    order = torch.argsort(rec["steps"][0], descending=True).to(torch.int32)
+    g = api.pn_integrate_adjoint(d["m"], pop["omega_f"], rec, gy, order=order)
+    torch.cuda.synchronize()
+    assert bool((rec["status"] == 0).all())
+    idx = np.sort(np.random.default_rng(K).choice(n, 64, replace=False))
+    sub = P.subset(pop, idx)
+    tape = rec["tape"].cpu().numpy()[idx]
+    replay = {"h": np.ascontiguousarray(tape[:, 2:2 + 1024]), "n_t": tape[:, 0].astype(np.int32),
+              "n_w": tape[:, 1].astype(np.int32)}
+    rng = np.random.default_rng(K + 1)
+    dm, dS, dL = (rng.normal(size=(c, 64)) * 1e-2 for c in (2, 6, 3))
+    dw = rng.normal(size=64) * 1e-5
+    tg = oracle.tangent(sub["m"], sub["S"], sub["L"], sub["omega0"], dm, dS, dL, dw, pop["omega_f"], pop["tol"],
+                        replay, nthreads=8)
+    gys = gy.cpu().numpy()[:, idx]
+    gg = {k: v.cpu().numpy()[..., idx] for k, v in g.items()}
+    lhs = (gg["m"] * dm).sum(0) + (gg["S0"] * dS).sum(0) + (gg["L0"] * dL).sum(0) + gg["omega0"] * dw
+    rhs = (gys * tg["dy"]).sum(0)
+    scale = np.abs(gg["m"] * dm).sum(0) + np.abs(gg["S0"] * dS).sum(0) + np.abs(gg["L0"] * dL).sum(0) \
+        + np.abs(gg["omega0"] * dw) + np.abs(gys * tg["dy"]).sum(0)
+    assert (np.abs(lhs - rhs) / scale).max() < 1e-9
