@@ -79,3 +79,26 @@ def test_fp32split_status_codes():
     assert (rg["status"][3:] == 0).all()
     r2 = run_gpu(pop, precision="fp32split", max_steps=5)
     assert (r2["status"][3:] == -1).all()
+
+
+def test_fp32split_full_size_samples():
+    """The whole 1M population in FP32-split, in the benchmark's launch
+    configuration, checked on 512 sampled inspirals against the FP64 oracle
+    with the bounds above."""
+    from paper_0908_3889_amd import api
+    pop = P.generate("q1to4_1M")
+    d = api.to_device(pop)
+    out = api.pn_integrate(d["m"], d["S"], d["L"], d["omega0"], pop["omega_f"], pop["tol"],
+                           api.make_opts(precision="fp32split"))
+    torch.cuda.synchronize()
+    st = out["status"].cpu().numpy()
+    assert (st == 0).all()
+    assert bool((out["y"][0] == pop["omega_f"]).all())
+    idx = np.sort(np.random.default_rng(31).choice(st.size, 512, replace=False))
+    ro = run_oracle(P.subset(pop, idx))
+    dots = out["dots"].cpu().numpy()[:, idx]
+    d_err = np.abs(dots - ro["dots"])
+    print("FP32-split full size, 512 samples: max", d_err.max(axis=1), "p99", np.percentile(d_err, 99, axis=1))
+    assert (d_err.max(axis=1) < 2e-4).all() and (np.percentile(d_err, 99, axis=1) < 5e-5).all()
+    t = out["t"].cpu().numpy()[idx]
+    assert np.abs(t / ro["t"] - 1).max() < 1e-5

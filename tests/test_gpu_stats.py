@@ -159,3 +159,31 @@ def test_statistics_of_the_paper_equal_mass_population():
         assert st["ks"][c, 0].item() == ks["D"]
     r = st["pearson"][:, 4].cpu().numpy()
     assert abs(r[0] - 0.99) < 0.01 and abs(r[1] - 0.65) < 0.03 and abs(r[2] - 0.65) < 0.03
+
+
+def test_statistics_full_size_workload():
+    """The statistics stage over the whole 1M workload's GPU dot products
+    (the benchmark's --stats input), against the oracle's statistics of the
+    same values."""
+    api = _api()
+    pop = P.generate("q1to4_1M")
+    d = api.to_device(pop)
+    out = api.pn_integrate(d["m"], d["S"], d["L"], d["omega0"], pop["omega_f"], pop["tol"])
+    y0 = torch.cat([d["omega0"][None], d["S"], d["L"]], 0).contiguous()
+    init = api.pn_observables(y0)
+    st = api.statistics(init, out["dots"])
+    torch.cuda.synchronize()
+    xi, xf = init.cpu().numpy(), out["dots"].cpu().numpy()
+    h100 = api.pn_histogram(out["dots"], 100).cpu().numpy()
+    grid = S.kde_grid(-1.0, 1.0, 201)
+    for c in range(3):
+        np.testing.assert_array_equal(st["hist"][c].cpu().numpy(), S.histogram(xf[c], -1.0, 1.0, 20))
+        np.testing.assert_array_equal(h100[c], S.histogram(xf[c], -1.0, 1.0, 100))
+        np.testing.assert_array_equal(st["hist2d"][c].cpu().numpy(), S.histogram2d(xi[c], xf[c], -1.0, 1.0, 79))
+        ref = S.pearson(xi[c], xf[c])
+        assert st["pearson"][c, 4].item() == pytest.approx(ref["r"], rel=1e-12)
+        np.testing.assert_allclose(st["kde"][c].cpu().numpy(), S.kde(xf[c], grid, S.silverman_bandwidth(xf[c])),
+                                   rtol=1e-11)
+        ks = S.ks_uniform(xf[c], -1.0, 1.0)
+        assert st["ks"][c, 0].item() == ks["D"]
+        assert st["ks"][c, 1].item() == pytest.approx(ks["p"], rel=1e-12, abs=1e-300)
