@@ -230,9 +230,14 @@ int pn_integrate_record(int64_t n, int64_t ld,
  *     bytes (the replayed states of one checkpoint segment per inspiral);
  *   order: optional device permutation of [0, n) giving the order in which
  *     inspirals are assigned to lanes (e.g. sorted by step count, so that a
- *     wave's lanes run segments of equal length); NULL = identity.
+ *     wave's lanes run segments of equal length); NULL = identity.  Entries
+ *     outside [0, n) are skipped, so an inspiral that a non-permutation
+ *     misses gets no output.
  * Inspirals with status DONE_AT_START get the identity (dL/dS0 = gy, ...,
- * dL/dm = 0); any other non-OK status gets NaN.
+ * dL/dm = 0); any other non-OK status gets NaN, and so does an OK inspiral
+ * whose tape row does not hold the counts of a recorded run (non-integer or
+ * negative, or more than cap_steps steps): the tape is never read beyond
+ * its row.
  */
 size_t pn_adjoint_workspace_bytes(int64_t n, int32_t ckpt_every);
 int pn_integrate_adjoint(int64_t n, int64_t ld, const double* m, double omega_f, const pn_opts* opt,

@@ -905,9 +905,14 @@ __device__ void adjoint_one(const AdjIo& io, const AdjUni& u, int64_t idx, doubl
     double lam[10];
 #pragma unroll
     for (int c = 0; c < 10; ++c) lam[c] = io.gy[c * ld + idx];
-    if (st == PN_ST_DONE_AT_START || st != PN_ST_OK) {
+    // the step counts of the tape must be those of a recorded run: integers
+    // with n_t + n_w <= cap (else the tape is not read beyond its row)
+    const double tnt = tp[0], tnw = tp[1];
+    const bool tape_ok = tnt >= 0.0 && tnw >= 0.0 && tnt + tnw <= (double)u.tape_cap &&
+                         tnt == __builtin_floor(tnt) && tnw == __builtin_floor(tnw);
+    if (st == PN_ST_DONE_AT_START || st != PN_ST_OK || !tape_ok) {
         // done at start: the output is the input; failures: no gradient
-        const double fill = (st == PN_ST_DONE_AT_START) ? 1.0 : __builtin_nan("");
+        const double fill = (st == PN_ST_DONE_AT_START) ? 1.0 : __builtin_nan("");   // (a bad tape: NaN)
         io.g_m[idx] = st == PN_ST_DONE_AT_START ? 0.0 : fill;
         io.g_m[ld + idx] = st == PN_ST_DONE_AT_START ? 0.0 : fill;
         io.g_w0[idx] = lam[0] * fill;
@@ -924,8 +929,8 @@ __device__ void adjoint_one(const AdjIo& io, const AdjUni& u, int64_t idx, doubl
 #pragma unroll
     for (int i = 0; i < NROW; ++i) rb.v[i] = 0.0;
     const double lt = io.gt ? io.gt[idx] : 0.0;
-    const int nt = (int)tp[0];
-    const int N = nt + (int)tp[1];
+    const int nt = (int)tnt;
+    const int N = nt + (int)tnw;
     const int K = u.ckpt_every;
     const double* hs = tp + 2;
     const double* ck = tp + 2 + u.tape_cap;
@@ -992,6 +997,7 @@ __global__ __launch_bounds__(BLOCK) void adjoint_kernel(AdjIo io, AdjUni u) {
     const int64_t j = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
     if (j >= u.n) return;
     const int64_t idx = io.order ? (int64_t)io.order[j] : j;
+    if (idx < 0 || idx >= u.n) return;      // not a permutation entry: nothing to do
 #if !PN_ADJ_Y_LDS
     // the stage-point scratch row of grid lane j: entry e at ystage[e * n + j]
     double* ys = io.ystage + j;
