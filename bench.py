@@ -35,8 +35,8 @@ METRIC = "inspirals/s to ω_f at 1e-8 tol; RHS evals/s as % VALU peak; adjoint/f
 F_RHS = 134
 F_STEP_COMB = 704
 FP64_VECTOR_PEAK_TFLOPS = 78.6      # MI355X: 256 CU x 2.4 GHz x 128 FLOP/clk
-FP32_VECTOR_PEAK_TFLOPS = 157.3     # MI355X datasheet (counts packed FP32; packed FP32
-                                    # instructions are disabled in this build, so half of
+FP32_VECTOR_PEAK_TFLOPS = 157.3     # MI355X datasheet (counts packed FP32; the library is
+                                    # compiled without packed FP32 instructions, so half of
                                     # it is the reachable ceiling)
 HBM_PEAK_GBS = 8000.0
 
@@ -328,8 +328,8 @@ def main() -> int:
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (--gpus {args.gpus} requested); "
-              "the inspirals are independent and would shard by index, see the design notes",
+        print(f"bench.py: the library runs on one GPU only (--gpus {args.gpus} requested); "
+              "the inspirals are independent and would shard by index range across GPUs",
               file=sys.stderr)
         return 2
 

@@ -27,8 +27,7 @@
  *     omega enter, and Phi is left out of the error norm, so the step
  *     sequence is the one without it.
  *
- * Readings taken where the paper is silent or ambiguous (each is repeated in
- * the design notes of the repository):
+ * Readings taken where the paper is silent or ambiguous:
  *   R1  the 3PN term: theta_hat multiplies eta once, i.e. the bracket is
  *       (-273811877/1088640 + 451/48 pi^2 - 88/3 theta_hat) eta; the literal
  *       printed form with an extra factor eta is available as a flag;
@@ -50,7 +49,9 @@
  *       stepper and controller, each omega-step clipped to the distance
  *       left, ending exactly at omega = omega_f;
  *   R11 no renormalisation of S_i or L_hat during the integration;
- *   R12 observables use the current vector norms and are 0 when a norm is 0.
+ *   R12 observables use the current vector norms and are 0 when a norm is 0;
+ *   R21 the orbital phase (not a quantity of the paper) is the integral of
+ *       omega dt from 0, taken on the accepted steps as described above.
  *
  * Parity unpinned: the paper prints no trajectory, no step count and no
  * controller constants, so the step sequence itself (R7, R8, R10) is pinned
