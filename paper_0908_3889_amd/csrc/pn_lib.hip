@@ -575,41 +575,54 @@ __device__ __forceinline__ int lane_id() { return __builtin_amdgcn_mbcnt_hi(~0u,
 __device__ __forceinline__ uint64_t wave_ballot(bool p) { return __ballot(p); }
 
 // Persistent loop: each wave hands new inspirals to idle lanes from a global
-// counter, until the counter passes n and its lanes are done.
+// counter, until the counter passes n and its lanes are done.  A lane that
+// finishes keeps its final state and status until the wave's next refill
+// pass, which first writes the outputs of all such lanes at once (the output
+// code then runs once per pass rather than once per finishing step); once
+// the counter is exhausted, every iteration with an idle lane is such a
+// pass, so the last outputs are written before the wave exits.
 template <class P>
 __device__ __forceinline__ void persistent_loop(const Io& io, const Uni& u, unsigned long long* counter) {
     const int lane = lane_id();
     typename P::LaneT L{};      // idle lanes step on this state and discard the result
     L.y[0] = 1.0;               // a positive omega keeps their arithmetic finite
     bool active = false;
+    // A finished lane whose outputs are not yet written keeps its status in
+    // L.h, which it no longer needs: L.h = -(status + kPend) < 0 (statuses
+    // are 1 and -1 .. -6; a lane that is idle otherwise has L.h >= 0).
+    constexpr int kPend = 16;
     bool exhausted = false;     // wave-uniform
     for (;;) {
-        // ---- refill idle lanes --------------------------------------------------
-        if (!exhausted) {
-            uint64_t need = wave_ballot(!active);
-            const int nidle = __popcll(need);
-            if (need != 0 && (nidle >= u.refill_min || nidle == 64)) {
-                while (need != 0 && !exhausted) {
-                    const int cnt = __popcll(need);
-                    const int leader = __ffsll((unsigned long long)need) - 1;
-                    unsigned long long base = 0;
-                    if (lane == leader) base = atomicAdd(counter, (unsigned long long)cnt);
-                    const unsigned lo = __builtin_amdgcn_readlane((unsigned)(base & 0xffffffffu), leader);
-                    const unsigned hi = __builtin_amdgcn_readlane((unsigned)(base >> 32), leader);
-                    base = ((unsigned long long)hi << 32) | lo;
-                    bool still = false;
-                    if (!active) {
-                        const unsigned rank = __builtin_amdgcn_mbcnt_hi((unsigned)(need >> 32),
-                                              __builtin_amdgcn_mbcnt_lo((unsigned)need, 0u));
-                        const unsigned long long idx = base + rank;
-                        if (idx < (unsigned long long)u.n) {
-                            const int st = P::load(io, u, L, (int64_t)idx);
-                            if (st == 0) active = true; else still = true;
-                        }
+        uint64_t need = wave_ballot(!active);
+        const int nidle = __popcll(need);
+        if (need != 0 && (exhausted || nidle >= u.refill_min || nidle == 64)) {
+            // ---- outputs of the lanes that finished since the last pass ------------
+            if (!active && L.h < 0.0) {
+                const int r = -(int)L.h - kPend;
+                P::finish(io, u, L, r == 1 ? PN_ST_OK : r);
+                L.h = 0.0;
+            }
+            // ---- refill idle lanes ------------------------------------------------
+            while (need != 0 && !exhausted) {
+                const int cnt = __popcll(need);
+                const int leader = __ffsll((unsigned long long)need) - 1;
+                unsigned long long base = 0;
+                if (lane == leader) base = atomicAdd(counter, (unsigned long long)cnt);
+                const unsigned lo = __builtin_amdgcn_readlane((unsigned)(base & 0xffffffffu), leader);
+                const unsigned hi = __builtin_amdgcn_readlane((unsigned)(base >> 32), leader);
+                base = ((unsigned long long)hi << 32) | lo;
+                bool still = false;
+                if (!active) {
+                    const unsigned rank = __builtin_amdgcn_mbcnt_hi((unsigned)(need >> 32),
+                                          __builtin_amdgcn_mbcnt_lo((unsigned)need, 0u));
+                    const unsigned long long idx = base + rank;
+                    if (idx < (unsigned long long)u.n) {
+                        const int st = P::load(io, u, L, (int64_t)idx);
+                        if (st == 0) active = true; else still = true;
                     }
-                    if (base + cnt >= (unsigned long long)u.n) exhausted = true;
-                    need = wave_ballot(still);
                 }
+                if (base + cnt >= (unsigned long long)u.n) exhausted = true;
+                need = wave_ballot(still);
             }
         }
         if (wave_ballot(active) == 0) {
@@ -620,7 +633,7 @@ __device__ __forceinline__ void persistent_loop(const Io& io, const Uni& u, unsi
         const bool any_w = wave_ballot(active && L.omega_mode) != 0;
         const int r = P::step(u, L, active, any_w);
         if (active && r != 0) {
-            P::finish(io, u, L, r == 1 ? PN_ST_OK : r);
+            L.h = -(double)(r + kPend);
             active = false;
         }
     }
