@@ -950,7 +950,20 @@ __device__ void adjoint_one(const AdjIo& io, const AdjUni& u, int64_t idx, doubl
     const int64_t wstride = u.n;
 #define WS(K_, C_) wsl[((int64_t)(K_) * 11 + (C_)) * wstride]
     const int nseg = (N + K - 1) / K;
-    for (int sg = nseg - 1; sg >= 0; --sg) {
+    // The lanes of a wave walk their segments in step: iteration sg handles
+    // segment sg on every lane that has one, counting down from the wave's
+    // largest segment count.  Counting down from each lane's own count would
+    // pair one lane's short last segment with another's full one, and a wave
+    // whose lanes straddle a multiple of K would take up to ~1.5x its longest
+    // inspiral.  The wave maximum is taken bit by bit with ballots, over the
+    // lanes still running (those that returned above take no part).
+    int nmax = 0;
+    for (int b = 28; b >= 0; --b) {        // nseg <= cap_steps <= 2^28
+        const int cand = nmax | (1 << b);
+        if (__ballot(nseg >= cand) != 0) nmax = cand;
+    }
+    for (int sg = nmax - 1; sg >= 0; --sg) {
+        if (sg >= nseg) continue;           // this lane has no segment sg
         const int k0 = sg * K;
         const int k1 = (k0 + K < N) ? k0 + K : N;
         double y[10];
