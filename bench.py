@@ -50,9 +50,13 @@ def algorithmic_flops(steps: np.ndarray) -> float:
     return float((nrhs * F_RHS).sum() + (attempted * F_STEP_COMB).sum())
 
 
-def cpu_baseline(pop: dict, budget_s: float = 12.0) -> dict:
+def cpu_baseline(pop: dict, budget_s: float = 12.0, gpu: dict | None = None, dot_tol: float = 1e-8) -> dict:
     """The oracle, as it stands, on a bounded prefix of the same workload,
-    on every host core this process may use."""
+    on every host core this process may use.  With the GPU's outputs for the
+    population (`gpu`: numpy dots [3, n], steps [3, n], status [n]) the
+    sample is also compared with them, as the paper checked its GPU runs
+    against the CPU on a subset (Sec. III): statuses, accepted and rejected
+    step counts, and the final dot products to dot_tol."""
     import oracle
     from paper_0908_3889_amd import population as P
 
@@ -69,9 +73,25 @@ def cpu_baseline(pop: dict, budget_s: float = 12.0) -> dict:
     r = oracle.integrate(sub["m"], sub["S"], sub["L"], sub["omega0"], pop["omega_f"], pop["tol"],
                          nthreads=cores)
     dt = time.perf_counter() - t0
-    return {"value": n_s / dt, "unit": "inspirals/s", "cores": cores, "kind": "oracle",
-            "sample": f"first {n_s} of {pop['n']} inspirals of {pop['workload']}, {dt:.1f} s",
-            "rhs_evals_per_s": float(r["steps"][2].sum()) / dt}
+    res = {"value": n_s / dt, "unit": "inspirals/s", "cores": cores, "kind": "oracle",
+           "sample": f"first {n_s} of {pop['n']} inspirals of {pop['workload']}, {dt:.1f} s",
+           "rhs_evals_per_s": float(r["steps"][2].sum()) / dt}
+    if gpu is not None:
+        res["crosscheck"] = crosscheck(r, {k: v[..., :n_s] for k, v in gpu.items()}, dot_tol)
+    return res
+
+
+def crosscheck(ref: dict, gpu: dict, dot_tol: float) -> dict:
+    """GPU outputs against the oracle's on the same inspirals."""
+    import oracle
+    dots = oracle.observables(ref["y"])
+    both = (ref["status"] == 0) & (gpu["status"] == 0)
+    dd = np.abs(gpu["dots"][:, both] - dots[:, both])
+    max_dd = float(dd.max()) if dd.size else 0.0
+    status_diff = int((ref["status"] != gpu["status"]).sum())
+    steps_diff = int(((ref["steps"][0] != gpu["steps"][0]) | (ref["steps"][1] != gpu["steps"][1])).sum())
+    return {"n": int(ref["status"].size), "status_mismatches": status_diff, "step_count_mismatches": steps_diff,
+            "max_dot_diff": max_dd, "dot_tol": dot_tol, "ok": bool(status_diff == 0 and max_dd < dot_tol)}
 
 
 PROFILES = os.path.join(ROOT, "profiles")
@@ -448,7 +468,9 @@ def main() -> int:
             res["error_vs_fp64"]["phase_rel_max"] = float(pr.max())
             res["error_vs_fp64"]["phase_rel_p99"] = float(np.percentile(pr, 99))
     if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(pop, args.cpu_budget)
+        gpu = {"dots": out["dots"].cpu().numpy(), "steps": steps, "status": status}
+        # FP32-split is checked against the FP64 oracle with its own error bound
+        res["cpu_baseline"] = cpu_baseline(pop, args.cpu_budget, gpu, 1e-8 if precision == "fp64" else 2e-4)
     print(json.dumps(res), flush=True)
     return 0
 

@@ -75,3 +75,38 @@ def test_bench_line_on_the_gpu():
     assert 0 < rf["frac"] < 1 and abs(rf["frac"] - rf["achieved"] / rf["peak"]) < 1e-12
     assert res["kernel"] == "integrate_persistent_f64"
     assert res["accepted_steps"] > 0 and res["kernel_ms"] > 0
+
+
+@pytest.mark.gpu
+def test_bench_cpu_baseline_and_crosscheck_on_the_gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    r = subprocess.run([sys.executable, "-u", os.path.join(ROOT, "bench.py"), "--workload", "equal_mass_maxspin_1k",
+                        "--steps", "2", "--warmup", "1", "--cpu-budget", "1"], capture_output=True, text=True,
+                       cwd=ROOT, timeout=300)
+    assert r.returncode == 0, r.stderr[-2000:]
+    cb = json.loads(r.stdout.strip().splitlines()[-1])["cpu_baseline"]
+    assert cb["kind"] == "oracle" and cb["value"] > 0
+    cc = cb["crosscheck"]
+    assert cc["ok"] and cc["n"] > 0 and cc["status_mismatches"] == 0 and cc["step_count_mismatches"] == 0
+    assert cc["max_dot_diff"] < 1e-8
+
+
+def test_cpu_baseline_crosscheck_flags_disagreement():
+    import oracle
+    pop = P.generate("equal_mass_maxspin_1k", 48)
+    r = oracle.integrate(pop["m"], pop["S"], pop["L"], pop["omega0"], pop["omega_f"], pop["tol"])
+    gpu = {"dots": oracle.observables(r["y"]), "steps": r["steps"].astype(np.int32), "status": r["status"]}
+    cc = bench.cpu_baseline(pop, budget_s=0.05, gpu=gpu)["crosscheck"]
+    assert cc["ok"] and cc["n"] == 48 and cc["max_dot_diff"] == 0.0
+    assert cc["status_mismatches"] == 0 and cc["step_count_mismatches"] == 0
+    bad = {k: v.copy() for k, v in gpu.items()}
+    bad["dots"][1, 5] += 1e-6
+    bad["steps"][0, 7] += 1
+    cc = bench.cpu_baseline(pop, budget_s=0.05, gpu=bad)["crosscheck"]
+    assert not cc["ok"] and abs(cc["max_dot_diff"] - 1e-6) < 1e-12 and cc["step_count_mismatches"] == 1
+    bad = {k: v.copy() for k, v in gpu.items()}
+    bad["status"][3] = -1
+    cc = bench.cpu_baseline(pop, budget_s=0.05, gpu=bad)["crosscheck"]
+    assert not cc["ok"] and cc["status_mismatches"] == 1
