@@ -102,6 +102,19 @@ struct Io {
     double* __restrict__ phase;   // orbital phase at t_final, or null
 };
 
+// What a persistent launch reads only when it refills lanes or writes
+// outputs; kept in device memory (the call's slot) instead of kernel
+// arguments, so that these values do not occupy scalar registers in the
+// step loop.
+struct LaunchDesc {
+    Io io;
+    Uni u;
+};
+constexpr int kDescOffset = 32;   // words: the counter, then padding to 256 B (its own cache lines)
+constexpr int kSlotWords = 64;    // 512 B per call slot
+static_assert(sizeof(LaunchDesc) / 8 + kDescOffset <= kSlotWords, "launch descriptor does not fit its slot");
+static_assert(sizeof(LaunchDesc) % 8 == 0 && sizeof(LaunchDesc) / 8 <= 64, "descriptor copy uses one word per thread");
+
 __device__ __forceinline__ bool finite(double v) { return __builtin_isfinite(v); }
 
 template <bool PHASE = false>
@@ -582,8 +595,9 @@ __device__ __forceinline__ uint64_t wave_ballot(bool p) { return __ballot(p); }
 // the counter is exhausted, every iteration with an idle lane is such a
 // pass, so the last outputs are written before the wave exits.
 template <class P>
-__device__ __forceinline__ void persistent_loop(const Io& io, const Uni& u, unsigned long long* counter) {
+__device__ __forceinline__ void persistent_loop(const Uni& u, unsigned long long* slot) {
     const int lane = lane_id();
+    unsigned long long* counter = slot;
     typename P::LaneT L{};      // idle lanes step on this state and discard the result
     L.y[0] = 1.0;               // a positive omega keeps their arithmetic finite
     bool active = false;
@@ -596,10 +610,17 @@ __device__ __forceinline__ void persistent_loop(const Io& io, const Uni& u, unsi
         uint64_t need = wave_ballot(!active);
         const int nidle = __popcll(need);
         if (need != 0 && (exhausted || nidle >= u.refill_min || nidle == 64)) {
+            // The inputs, outputs and the arguments only a refill needs are read
+            // from the launch descriptor in the call's slot here, rather than
+            // kept in scalar registers across the step loop, which needs them all.
+            const LaunchDesc* d = reinterpret_cast<const LaunchDesc*>(slot + kDescOffset);
+            asm volatile("" : "+s"(d));        // keep the loads inside the pass
+            const Io& io = d->io;
+            const Uni& uc = d->u;
             // ---- outputs of the lanes that finished since the last pass ------------
             if (!active && L.h < 0.0) {
                 const int r = -(int)L.h - kPend;
-                P::finish(io, u, L, r == 1 ? PN_ST_OK : r);
+                P::finish(io, uc, L, r == 1 ? PN_ST_OK : r);
                 L.h = 0.0;
             }
             // ---- refill idle lanes ------------------------------------------------
@@ -617,7 +638,7 @@ __device__ __forceinline__ void persistent_loop(const Io& io, const Uni& u, unsi
                                           __builtin_amdgcn_mbcnt_lo((unsigned)need, 0u));
                     const unsigned long long idx = base + rank;
                     if (idx < (unsigned long long)u.n) {
-                        const int st = P::load(io, u, L, (int64_t)idx);
+                        const int st = P::load(io, uc, L, (int64_t)idx);
                         if (st == 0) active = true; else still = true;
                     }
                 }
@@ -659,27 +680,27 @@ __device__ __forceinline__ void static_loop(const Io& io, const Uni& u, int64_t 
 
 template <int BLOCK, bool RECORD>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(PN_WPE_F64)))
-void integrate_persistent_f64(Io io, Uni u, unsigned long long* counter) {
-    persistent_loop<F64<RECORD>>(io, u, counter);
+void integrate_persistent_f64(Uni u, unsigned long long* slot) {
+    persistent_loop<F64<RECORD>>(u, slot);
 }
 
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(PN_WPE_F32)))
-void integrate_persistent_f32s(Io io, Uni u, unsigned long long* counter) {
-    persistent_loop<F32Split<>>(io, u, counter);
+void integrate_persistent_f32s(Uni u, unsigned long long* slot) {
+    persistent_loop<F32Split<>>(u, slot);
 }
 
 // the same loops with the orbital phase integrated alongside
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(PN_WPE_F64)))
-void integrate_persistent_f64_phase(Io io, Uni u, unsigned long long* counter) {
-    persistent_loop<F64<false, true>>(io, u, counter);
+void integrate_persistent_f64_phase(Uni u, unsigned long long* slot) {
+    persistent_loop<F64<false, true>>(u, slot);
 }
 
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(PN_WPE_F32)))
-void integrate_persistent_f32s_phase(Io io, Uni u, unsigned long long* counter) {
-    persistent_loop<F32Split<true>>(io, u, counter);
+void integrate_persistent_f32s_phase(Uni u, unsigned long long* slot) {
+    persistent_loop<F32Split<true>>(u, slot);
 }
 
 template <int BLOCK, bool RECORD>
@@ -1032,7 +1053,14 @@ __global__ __launch_bounds__(BLOCK) void adjoint_kernel(AdjIo io, AdjUni u) {
     adjoint_one(io, u, idx, io.ws + j, ys, ystride, ms);
 }
 
-__global__ void reset_counter(unsigned long long* c) { *c = 0ull; }
+// Zeroes the work counter of a persistent launch and writes its launch
+// descriptor into the call's slot (one word per thread).
+__global__ void prepare_launch(unsigned long long* slot, LaunchDesc desc) {
+    const unsigned t = threadIdx.x;
+    if (t == 0) slot[0] = 0ull;
+    const unsigned long long* src = reinterpret_cast<const unsigned long long*>(&desc);
+    if (t < sizeof(LaunchDesc) / 8) slot[kDescOffset + t] = src[t];
+}
 
 __global__ void rhs_kernel(int64_t n, int64_t ld, const double* __restrict__ m, const double* __restrict__ y,
                            double* __restrict__ d, int terms, int theta_literal, TermConsts tc) {
@@ -1075,7 +1103,7 @@ constexpr int kCounterSlots = 1024;
 struct DevCtx {
     std::atomic<bool> ready{false};
     int cus = 0;
-    unsigned long long* counters = nullptr;   // kCounterSlots work counters
+    unsigned long long* counters = nullptr;   // kCounterSlots slots: work counter, launch descriptor
     std::atomic<unsigned> next{0};
 };
 
@@ -1095,7 +1123,8 @@ int get_ctx(DevCtx** out) {
             if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return PN_ENODEV;
             c.cus = prop.multiProcessorCount;
             void* p = nullptr;
-            if (hipMalloc(&p, sizeof(unsigned long long) * kCounterSlots) != hipSuccess) return PN_ENOMEM;
+            if (hipMalloc(&p, sizeof(unsigned long long) * kCounterSlots * kSlotWords) != hipSuccess)
+                return PN_ENOMEM;
             c.counters = (unsigned long long*)p;
             c.ready.store(true, std::memory_order_release);
         }
@@ -1126,7 +1155,10 @@ hipError_t launch_forward(const Io& io, const Uni& u, int precision, int schedul
         else hipLaunchKernelGGL((integrate_static_f64<BLOCK, false>), dim3((unsigned)grid), dim3(BLOCK), 0, s, io, u);
         return hipGetLastError();
     }
-    hipLaunchKernelGGL(reset_counter, dim3(1), dim3(1), 0, s, counter);
+    LaunchDesc desc;
+    desc.io = io;
+    desc.u = u;
+    hipLaunchKernelGGL(prepare_launch, dim3(1), dim3(64), 0, s, counter, desc);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int64_t waves_needed = (u.n + 63) / 64;
@@ -1134,15 +1166,15 @@ hipError_t launch_forward(const Io& io, const Uni& u, int precision, int schedul
     if (waves > waves_needed) waves = waves_needed;
     const int64_t grid = (waves * 64 + BLOCK - 1) / BLOCK;
     if (ph && f32)
-        hipLaunchKernelGGL(integrate_persistent_f32s_phase<BLOCK>, dim3((unsigned)grid), dim3(BLOCK), 0, s, io, u, counter);
+        hipLaunchKernelGGL(integrate_persistent_f32s_phase<BLOCK>, dim3((unsigned)grid), dim3(BLOCK), 0, s, u, counter);
     else if (ph)
-        hipLaunchKernelGGL(integrate_persistent_f64_phase<BLOCK>, dim3((unsigned)grid), dim3(BLOCK), 0, s, io, u, counter);
+        hipLaunchKernelGGL(integrate_persistent_f64_phase<BLOCK>, dim3((unsigned)grid), dim3(BLOCK), 0, s, u, counter);
     else if (f32)
-        hipLaunchKernelGGL(integrate_persistent_f32s<BLOCK>, dim3((unsigned)grid), dim3(BLOCK), 0, s, io, u, counter);
+        hipLaunchKernelGGL(integrate_persistent_f32s<BLOCK>, dim3((unsigned)grid), dim3(BLOCK), 0, s, u, counter);
     else if (u.tape)
-        hipLaunchKernelGGL((integrate_persistent_f64<BLOCK, true>), dim3((unsigned)grid), dim3(BLOCK), 0, s, io, u, counter);
+        hipLaunchKernelGGL((integrate_persistent_f64<BLOCK, true>), dim3((unsigned)grid), dim3(BLOCK), 0, s, u, counter);
     else
-        hipLaunchKernelGGL((integrate_persistent_f64<BLOCK, false>), dim3((unsigned)grid), dim3(BLOCK), 0, s, io, u, counter);
+        hipLaunchKernelGGL((integrate_persistent_f64<BLOCK, false>), dim3((unsigned)grid), dim3(BLOCK), 0, s, u, counter);
     return hipGetLastError();
 }
 
@@ -1236,7 +1268,7 @@ static int integrate_impl(int64_t n, int64_t ld, const double* m, const double* 
     io.y = y_final; io.t = t_final; io.steps = steps; io.status = status; io.dots = dots;
     io.phase = phase;
 
-    unsigned long long* counter = ctx->counters + (ctx->next.fetch_add(1) % kCounterSlots);
+    unsigned long long* counter = ctx->counters + (size_t)(ctx->next.fetch_add(1) % kCounterSlots) * kSlotWords;
     hipStream_t s = (hipStream_t)stream;
     hipError_t e;
     switch (block) {
