@@ -31,8 +31,11 @@
  *    names a code.
  *  - Outcomes per inspiral go to status[i] (PN_ST_*), never to the return code.
  *  - Safe to call from several host threads on different streams.  The
- *    library keeps a small per-device context (a work counter per call slot
- *    and the device's compute-unit count), created on first use.
+ *    library keeps a small per-device context (1024 call slots of 512 bytes,
+ *    each a work counter and the launch arguments of a persistent launch,
+ *    and the device's compute-unit count), created on first use.  Calls
+ *    take the slots in turn, so at most 1024 persistent launches may be in
+ *    flight at once across all streams of a device.
  */
 #ifndef PN_H
 #define PN_H
