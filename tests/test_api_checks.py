@@ -51,3 +51,24 @@ def test_adjoint_refuses_host_and_strided_arrays():
     rec = {"status": torch.zeros(4, dtype=torch.int32), "ckpt_every": 16}
     with pytest.raises(TypeError):
         api.pn_integrate_adjoint(_host(2, 4), 0.05, rec, _host(10, 4))
+
+
+def test_missing_library_fails_loudly_and_the_package_never_imports_the_oracle():
+    """Without libpn.so the binding raises (there is no CPU fallback), and
+    importing the package pulls in nothing from the oracle."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = ("import sys\n"
+            "from paper_0908_3889_amd import api, _lib, population\n"
+            "assert not any(m == 'oracle' or m.startswith('oracle.') for m in sys.modules), 'oracle imported'\n"
+            "try:\n"
+            "    _lib.load()\n"
+            "except _lib.PnError as e:\n"
+            "    assert 'no fallback' in str(e), e\n"
+            "    print('raised')\n")
+    env = dict(os.environ, PN_LIB=os.path.join(root, "no-such-dir", "libpn.so"))
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, cwd=root, env=env, timeout=300)
+    assert r.returncode == 0, r.stderr[-2000:]
+    assert r.stdout.strip() == "raised"
