@@ -467,6 +467,8 @@ def main() -> int:
             pr = np.abs(out["phase"].cpu().numpy() / out64["phase"].cpu().numpy() - 1)
             res["error_vs_fp64"]["phase_rel_max"] = float(pr.max())
             res["error_vs_fp64"]["phase_rel_p99"] = float(np.percentile(pr, 99))
+    # the datasheet peak above, checked on this device (sustained FMA rate)
+    res["vector_peak_probe"] = api.pn_fma_rate(8, 4000, stream=stream)
     if not args.no_cpu_baseline:
         gpu = {"dots": out["dots"].cpu().numpy(), "steps": steps, "status": status}
         # FP32-split is checked against the FP64 oracle with its own error bound

@@ -183,6 +183,18 @@ int pn_autotune(int64_t n, int64_t ld, const double* m, const double* S0, const 
                 double* dots, pn_opts* best, double* times_ms, void* stream);
 
 /*
+ * pn_fma_rate -- the device's sustained vector multiply-add rate, the
+ * measured counterpart of the datasheet peaks that roofline fractions are
+ * quoted against: eight independent FMA chains per lane, 16 x iters steps
+ * each, on CUs x waves_per_simd blocks of 256 threads (waves_per_simd
+ * 1..8, iters 1..2^20), in FP32 without packed instructions and in FP64.
+ * Writes TFLOP/s (an FMA counted as 2) to *fp32_tflops and *fp64_tflops
+ * (host pointers).  Allocates and frees a small device buffer and blocks
+ * until its timers are read.
+ */
+int pn_fma_rate(int32_t waves_per_simd, int32_t iters, double* fp32_tflops, double* fp64_tflops, void* stream);
+
+/*
  * pn_rhs -- Eqs. (1)-(4) evaluated pointwise, dy/dt at y, for testing the
  * right-hand side on its own.  m [2][ld], y [10][ld] -> dydt [10][ld].
  * `terms`/`theta_literal` as in pn_opts (opt may be NULL).

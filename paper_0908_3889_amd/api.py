@@ -255,6 +255,15 @@ class PNIntegrate(torch.autograd.Function):
         return g["m"], g["S0"], g["L0"], g["omega0"], None, None, None, None
 
 
+def pn_fma_rate(waves_per_simd: int = 8, iters: int = 4000, stream=None) -> dict:
+    """Sustained vector FMA rate of the current device in TFLOP/s: FP32
+    without packed instructions, and FP64 (blocks until measured)."""
+    f32, f64 = C.c_double(0.0), C.c_double(0.0)
+    rc = load().pn_fma_rate(int(waves_per_simd), int(iters), C.byref(f32), C.byref(f64), _stream(stream))
+    check(rc, "pn_fma_rate")
+    return {"fp32_nonpacked": f32.value, "fp64": f64.value, "unit": "TFLOP/s", "waves_per_simd": int(waves_per_simd)}
+
+
 def pn_rhs(m, y, opts: PnOpts | None = None, stream=None) -> torch.Tensor:
     """Eqs. (1)-(4) pointwise: m [2, n], y [10, n] -> dy/dt [10, n]."""
     n = int(y.shape[1])

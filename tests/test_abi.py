@@ -83,6 +83,11 @@ def test_invalid_arguments_return_einval_without_a_device(lib):
     assert ph(10, 10, fake, tol=-1.0) == PN_EINVAL
     assert ph(10, 5, fake) == PN_EINVAL
     assert ph(0, 0, z) == PN_OK
+    d1, d2 = C.c_double(0.0), C.c_double(0.0)
+    assert lib.pn_fma_rate(0, 100, C.byref(d1), C.byref(d2), z) == PN_EINVAL
+    assert lib.pn_fma_rate(9, 100, C.byref(d1), C.byref(d2), z) == PN_EINVAL
+    assert lib.pn_fma_rate(8, 0, C.byref(d1), C.byref(d2), z) == PN_EINVAL
+    assert lib.pn_fma_rate(8, 100, None, C.byref(d2), z) == PN_EINVAL
     big = 1 << 36                                    # PN_MAX_N
     assert call(big + 1, big + 1) == PN_EINVAL
     assert call(10, big + 1) == PN_EINVAL

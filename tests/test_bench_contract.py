@@ -75,6 +75,12 @@ def test_bench_line_on_the_gpu():
     assert 0 < rf["frac"] < 1 and abs(rf["frac"] - rf["achieved"] / rf["peak"]) < 1e-12
     assert res["kernel"] == "integrate_persistent_f64"
     assert res["accepted_steps"] > 0 and res["kernel_ms"] > 0
+    # the probe of the vector peak: FP32 without packed instructions and FP64
+    # both issue one wave64 FMA per four cycles per SIMD, the 78.6 TFLOP/s of
+    # the datasheet's FP64 figure (256 CUs x 2.4 GHz x 128 FLOP/clock)
+    pk = res["vector_peak_probe"]
+    for k in ("fp32_nonpacked", "fp64"):
+        assert 0.6 * 78.6 < pk[k] < 1.02 * 78.6, pk
 
 
 @pytest.mark.gpu
