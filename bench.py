@@ -76,6 +76,12 @@ def cpu_baseline(pop: dict, budget_s: float = 12.0, gpu: dict | None = None, dot
     res = {"value": n_s / dt, "unit": "inspirals/s", "cores": cores, "kind": "oracle",
            "sample": f"first {n_s} of {pop['n']} inspirals of {pop['workload']}, {dt:.1f} s",
            "rhs_evals_per_s": float(r["steps"][2].sum()) / dt}
+    # one host core on a small part of the same sample (about a tenth of the budget)
+    n1 = int(max(1, min(n_s, n_s / dt * budget_s / 10 / max(cores, 1))))
+    one = P.subset(pop, np.arange(n1))
+    t0 = time.perf_counter()
+    oracle.integrate(one["m"], one["S"], one["L"], one["omega0"], pop["omega_f"], pop["tol"], nthreads=1)
+    res["per_core"] = {"value": n1 / (time.perf_counter() - t0), "sample": f"first {n1} inspirals, one thread"}
     if gpu is not None:
         res["crosscheck"] = crosscheck(r, {k: v[..., :n_s] for k, v in gpu.items()}, dot_tol)
     return res

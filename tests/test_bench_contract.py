@@ -33,6 +33,7 @@ def test_cpu_baseline_fields():
     assert cb["value"] > 0 and cb["cores"] == len(os.sched_getaffinity(0))
     assert cb["sample"].startswith("first ") and "of 64 inspirals of equal_mass_maxspin_1k" in cb["sample"]
     assert cb["rhs_evals_per_s"] > cb["value"]
+    assert cb["per_core"]["value"] > 0 and "one thread" in cb["per_core"]["sample"]
 
 
 def test_algorithmic_flops_from_step_counts():
