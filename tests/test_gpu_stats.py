@@ -187,3 +187,35 @@ def test_statistics_full_size_workload():
         ks = S.ks_uniform(xf[c], -1.0, 1.0)
         assert st["ks"][c, 0].item() == ks["D"]
         assert st["ks"][c, 1].item() == pytest.approx(ks["p"], rel=1e-12, abs=1e-300)
+
+
+@pytest.mark.parametrize("ncomp", [1, 7, 16])
+def test_many_components(ncomp):
+    """Every statistic over up to the largest number of components a call
+    takes, each component its own distribution."""
+    api = _api()
+    rng = np.random.default_rng(ncomp)
+    n = 50021
+    x = np.stack([np.clip(rng.normal(-0.5 + c / ncomp, 0.2 + 0.02 * c, n), -1, 1) for c in range(ncomp)])
+    y = np.stack([0.5 * x[c] + 0.5 * rng.uniform(-1, 1, n) for c in range(ncomp)])
+    xt, yt = torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda()
+    h = api.pn_histogram(xt, 37).cpu().numpy()
+    h2 = api.pn_histogram2d(xt, yt, 23).cpu().numpy()
+    p = api.pn_pearson(xt, yt).cpu().numpy()
+    ks = api.pn_ks_uniform(xt).cpu().numpy()
+    kde = api.pn_kde(xt, api.pn_pearson(xt, xt)[:, 2].contiguous(), 64).cpu().numpy()
+    grid = S.kde_grid(-1.0, 1.0, 64)
+    for c in range(ncomp):
+        np.testing.assert_array_equal(h[c], S.histogram(x[c], -1.0, 1.0, 37))
+        np.testing.assert_array_equal(h2[c], S.histogram2d(x[c], y[c], -1.0, 1.0, 23))
+        assert abs(p[c, 4] - S.pearson(x[c], y[c])["r"]) < 1e-12
+        ref = S.ks_uniform(x[c], -1.0, 1.0)
+        assert ks[c, 0] == ref["D"]
+        np.testing.assert_allclose(kde[c], S.kde(x[c], grid, S.silverman_bandwidth(x[c])), rtol=1e-11, atol=1e-300)
+
+
+def test_too_many_components_is_refused():
+    api = _api()
+    x = torch.zeros((17, 10), dtype=torch.float64, device="cuda")
+    with pytest.raises(Exception):
+        api.pn_histogram(x, 10)
