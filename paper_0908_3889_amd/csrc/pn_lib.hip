@@ -212,10 +212,12 @@ __device__ __forceinline__ int pre_status(const Uni& u, const LaneT& L) {
 
 // The step to attempt, clipped to what is left of the omega stretch (or of
 // t_end); last = the clipped step ends the integration if accepted.
-template <class LaneT>
+// GEN = false: the kernel only runs adaptive integrations to omega_f (no
+// fixed step, no t_end), so those tests fold away.
+template <bool GEN, class LaneT>
 __device__ __forceinline__ double clip_step(const Uni& u, const LaneT& L, bool& last) {
-    const double remain = L.omega_mode ? u.omega_f - L.y[0] : u.t_end - L.t;
-    last = (L.omega_mode || u.tend) && L.h >= remain;
+    const double remain = L.omega_mode ? u.omega_f - L.y[0] : (GEN ? u.t_end - L.t : 0.0);
+    last = (L.omega_mode || (GEN && u.tend)) && L.h >= remain;
     return last ? remain : L.h;
 }
 
@@ -223,21 +225,22 @@ __device__ __forceinline__ double clip_step(const Uni& u, const LaneT& L, bool& 
 // on lanes with go = (active, no status before the step); other lanes keep
 // their state.  Y: candidate state, k7/dt7: its derivative, dts = sum_j b_j
 // dt_j (omega mode).  Returns 0 (continue), 1 (finished OK) or a status.
-template <bool RECORD, class LaneT, class KT>
+template <bool RECORD, bool GEN, class LaneT, class KT>
 __device__ __forceinline__ int control(const Uni& u, LaneT& L, bool go, int st, bool fin, double z, double h,
                                        bool last, const double* Y, const KT* k7, KT dt7, KT dts) {
+    const bool fixed = GEN && u.fixed, tend = GEN && u.tend;
     if (go && !fin) st = PN_ST_NONFINITE;
     const bool ok = go && fin;
-    const bool acc = ok && (u.fixed || z <= Z_ACCEPT);
+    const bool acc = ok && (fixed || z <= Z_ACCEPT);
     // a candidate past omega_f is discarded: the stretch is finished with
     // omega as the independent variable
-    const bool to_w = acc && !L.omega_mode && !u.tend && Y[0] > u.omega_f;
+    const bool to_w = acc && !L.omega_mode && !tend && Y[0] > u.omega_f;
     const bool take = acc && !to_w;
     const bool rej = ok && !acc;
     // step factor (safety 0.9, exponent 1/5, clamped to [0.2, 5], no growth
     // right after a rejection); one z^(-1/10) serves accepts and rejects
     double fac = 1.0;
-    if (!u.fixed) {
+    if (!fixed) {
         const double p = 0.9 * pow_m_tenth(__builtin_fmin(__builtin_fmax(z, 9.313225746154785e-10), 1.073741824e9));
         const double fa = __builtin_fmin(5.0, __builtin_fmax(0.2, p));
         fac = rej ? __builtin_fmax(0.2, p) : (L.last_rej ? __builtin_fmin(fa, 1.0) : fa);
@@ -260,7 +263,7 @@ __device__ __forceinline__ int control(const Uni& u, LaneT& L, bool go, int st, 
         if ((L.acc + 1) % u.ckpt_every == 0) tape_checkpoint(u, L.idx, (L.acc + 1) / u.ckpt_every, Y);
     }
     const double tn = L.omega_mode ? __builtin_fma(h, (double)dts, L.t) : L.t + h;
-    const bool done = take && (last || (!L.omega_mode && !u.tend && Y[0] == u.omega_f));
+    const bool done = take && (last || (!L.omega_mode && !tend && Y[0] == u.omega_f));
 #pragma unroll
     for (int c = 0; c < 10; ++c) {
         L.y[c] = take ? Y[c] : L.y[c];
@@ -271,7 +274,7 @@ __device__ __forceinline__ int control(const Uni& u, LaneT& L, bool go, int st, 
     L.dt1 = take ? dt7 : L.dt1;
     L.acc += take ? 1 : 0;
     L.rej += rej ? 1 : 0;
-    const bool resize = rej || (take && !done && !u.fixed);
+    const bool resize = rej || (take && !done && !fixed);
     L.h = resize ? h * fac : L.h;
     L.last_rej = resize ? rej : L.last_rej;
     const double scale = L.omega_mode ? __builtin_fabs(L.y[0]) : __builtin_fmax(1.0, __builtin_fabs(L.t));
@@ -299,7 +302,7 @@ struct LaneF64 {
 // PHASE: also integrate the orbital phase, d Phi/dt = omega, as a quadrature
 // on the same steps (5th-order weights on the stage values of omega times
 // dt/d(variable)), outside the error norm, so the steps are unchanged.
-template <bool RECORD, bool PHASE = false>
+template <bool RECORD, bool PHASE = false, bool GEN = true>
 struct F64 {
     using LaneT = LaneF64;
 
@@ -342,7 +345,7 @@ struct F64 {
         bool last;
         // idle lanes take a step of zero: their stage points stay on their
         // state, so they never send the wave down a slow path
-        const double h = active ? clip_step(u, L, last) : 0.0;
+        const double h = active ? clip_step<GEN>(u, L, last) : 0.0;
 
         const Row& R = L.row;
         const double* y = L.y;
@@ -425,11 +428,11 @@ struct F64 {
 #pragma unroll
         for (int c = 0; c < 10; ++c) e[c] = h * __builtin_fma(E7, k7[c], Ep[c]);
         const double z = error_norm(u, y, Y, e);
-        bool fin = u.fixed || !__builtin_isnan(z);
+        bool fin = (GEN && u.fixed) || !__builtin_isnan(z);
 #pragma unroll
         for (int c = 0; c < 10; ++c) fin = fin && finite(Y[c]);
         const int acc0 = L.acc;
-        const int r = control<RECORD>(u, L, go, st0, fin, z, h, last, Y, k7, dt7, dts);
+        const int r = control<RECORD, GEN>(u, L, go, st0, fin, z, h, last, Y, k7, dt7, dts);
         L.lnv = L.acc != acc0 ? lnv7 : L.lnv;
         if (PHASE) L.phase = L.acc != acc0 ? __builtin_fma(h, ps, L.phase) : L.phase;
         return r;
@@ -452,7 +455,7 @@ struct LaneF32 {
     bool omega_mode, last_rej;
 };
 
-template <bool PHASE = false>
+template <bool PHASE = false, bool GEN = true>
 struct F32Split {
     using LaneT = LaneF32;
 
@@ -489,7 +492,7 @@ struct F32Split {
         bool last;
         // idle lanes take a step of zero: their stage points stay on their
         // state, so they never send the wave down a slow path
-        const double h = active ? clip_step(u, L, last) : 0.0;
+        const double h = active ? clip_step<GEN>(u, L, last) : 0.0;
 
         const RowF& R = L.row;
         const float* k1 = L.k1;
@@ -569,11 +572,11 @@ struct F32Split {
 #pragma unroll
         for (int c = 0; c < 10; ++c) e[c] = (double)(hf * __builtin_fmaf((float)E7, k7[c], Ep[c]));
         const double z = error_norm(u, L.y, ynew, e);
-        bool fin = u.fixed || !__builtin_isnan(z);
+        bool fin = (GEN && u.fixed) || !__builtin_isnan(z);
 #pragma unroll
         for (int c = 0; c < 10; ++c) fin = fin && finite(ynew[c]) && __builtin_isfinite(k7[c]);
         const int acc0 = L.acc;
-        const int r = control<false>(u, L, go, st0, fin, z, h, last, ynew, k7, dt7, dts);
+        const int r = control<false, GEN>(u, L, go, st0, fin, z, h, last, ynew, k7, dt7, dts);
         // the FP32 increment is summed in FP64, as the state is
         if (PHASE) L.phase = L.acc != acc0 ? __builtin_fma(h, (double)ps, L.phase) : L.phase;
         return r;
@@ -681,13 +684,25 @@ __device__ __forceinline__ void static_loop(const Io& io, const Uni& u, int64_t 
 template <int BLOCK, bool RECORD>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(PN_WPE_F64)))
 void integrate_persistent_f64(Uni u, unsigned long long* slot) {
-    persistent_loop<F64<RECORD>>(u, slot);
+    persistent_loop<F64<RECORD, false, false>>(u, slot);      // adaptive, to omega_f
+}
+
+template <int BLOCK, bool RECORD>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(PN_WPE_F64)))
+void integrate_persistent_f64_modes(Uni u, unsigned long long* slot) {
+    persistent_loop<F64<RECORD, false, true>>(u, slot);       // also fixed step and t_end
 }
 
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(PN_WPE_F32)))
 void integrate_persistent_f32s(Uni u, unsigned long long* slot) {
-    persistent_loop<F32Split<>>(u, slot);
+    persistent_loop<F32Split<false, false>>(u, slot);
+}
+
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(PN_WPE_F32)))
+void integrate_persistent_f32s_modes(Uni u, unsigned long long* slot) {
+    persistent_loop<F32Split<false, true>>(u, slot);
 }
 
 // the same loops with the orbital phase integrated alongside
@@ -1165,16 +1180,24 @@ hipError_t launch_forward(const Io& io, const Uni& u, int precision, int schedul
     int64_t waves = (int64_t)cus * 4 * waves_per_simd;
     if (waves > waves_needed) waves = waves_needed;
     const int64_t grid = (waves * 64 + BLOCK - 1) / BLOCK;
+    const bool gen = u.fixed || u.tend;    // not the plain adaptive run to omega_f
+    const dim3 g((unsigned)grid), b(BLOCK);
     if (ph && f32)
-        hipLaunchKernelGGL(integrate_persistent_f32s_phase<BLOCK>, dim3((unsigned)grid), dim3(BLOCK), 0, s, u, counter);
+        hipLaunchKernelGGL(integrate_persistent_f32s_phase<BLOCK>, g, b, 0, s, u, counter);
     else if (ph)
-        hipLaunchKernelGGL(integrate_persistent_f64_phase<BLOCK>, dim3((unsigned)grid), dim3(BLOCK), 0, s, u, counter);
+        hipLaunchKernelGGL(integrate_persistent_f64_phase<BLOCK>, g, b, 0, s, u, counter);
+    else if (f32 && gen)
+        hipLaunchKernelGGL(integrate_persistent_f32s_modes<BLOCK>, g, b, 0, s, u, counter);
     else if (f32)
-        hipLaunchKernelGGL(integrate_persistent_f32s<BLOCK>, dim3((unsigned)grid), dim3(BLOCK), 0, s, u, counter);
+        hipLaunchKernelGGL(integrate_persistent_f32s<BLOCK>, g, b, 0, s, u, counter);
+    else if (u.tape && gen)
+        hipLaunchKernelGGL((integrate_persistent_f64_modes<BLOCK, true>), g, b, 0, s, u, counter);
     else if (u.tape)
-        hipLaunchKernelGGL((integrate_persistent_f64<BLOCK, true>), dim3((unsigned)grid), dim3(BLOCK), 0, s, u, counter);
+        hipLaunchKernelGGL((integrate_persistent_f64<BLOCK, true>), g, b, 0, s, u, counter);
+    else if (gen)
+        hipLaunchKernelGGL((integrate_persistent_f64_modes<BLOCK, false>), g, b, 0, s, u, counter);
     else
-        hipLaunchKernelGGL((integrate_persistent_f64<BLOCK, false>), dim3((unsigned)grid), dim3(BLOCK), 0, s, u, counter);
+        hipLaunchKernelGGL((integrate_persistent_f64<BLOCK, false>), g, b, 0, s, u, counter);
     return hipGetLastError();
 }
 
