@@ -293,3 +293,50 @@ def test_bad_tape_rows_and_order_entries_are_refused_per_inspiral():
     keep = np.setdiff1d(np.arange(n), [5, 6])
     for k in ("m", "S0", "L0", "omega0"):
         np.testing.assert_array_equal(g[k][..., keep], ref[k][..., keep])
+
+
+def test_central_differences_on_256_samples_of_the_differentiation_workload():
+    """The differentiation workload's check: the gradient of
+    L = sum S1.S2 + sum L_hat_z (final) against central differences
+    (h = 1e-6) of the oracle's replay of the GPU's recorded steps, for every
+    input component of 256 inspirals."""
+    from paper_0908_3889_amd import api
+    n = 256
+    pop = P.generate("adjoint_64k", n)
+    d, rec = _record(pop, K=64, cap=1024)
+    assert bool((rec["status"] == 0).all())
+    y = rec["y"]
+    gy = torch.zeros_like(y)
+    gy[1:4] = y[4:7]
+    gy[4:7] = y[1:4]
+    gy[9] = 1.0
+    g = {k: v.cpu().numpy() for k, v in api.pn_integrate_adjoint(d["m"], pop["omega_f"], rec, gy).items()}
+    torch.cuda.synchronize()
+    replay = _replay_of(rec)
+
+    def loss(m, S, L, w):
+        r = oracle.integrate(m, S, L, w, pop["omega_f"], pop["tol"], replay=replay, nthreads=8)
+        yy = r["y"]
+        return (yy[1:4] * yy[4:7]).sum(0) + yy[9]
+
+    eps = 1e-6
+    base = dict(m=pop["m"], S=pop["S"], L=pop["L"], w=pop["omega0"])
+    worst = 0.0
+    for name, comps, grad in (("m", 2, g["m"]), ("S", 6, g["S0"]), ("L", 3, g["L0"]), ("w", 1, g["omega0"][None])):
+        for c in range(comps):
+            plus = {k: v.copy() for k, v in base.items()}
+            minus = {k: v.copy() for k, v in base.items()}
+            if name == "w":
+                step = eps * pop["omega0"]
+                plus["w"] = plus["w"] + step
+                minus["w"] = minus["w"] - step
+                ad = grad[c] * pop["omega0"]
+            else:
+                plus[name][c] += eps
+                minus[name][c] -= eps
+                ad = grad[c]
+            fd = (loss(**plus) - loss(**minus)) / (2 * eps)
+            err = np.abs(fd - ad) / np.maximum(1.0, np.abs(ad))
+            worst = max(worst, float(err.max()))
+    print(f"adjoint vs central differences, 256 samples x 12 components: max rel err {worst:.2e}")
+    assert worst < 1e-6
