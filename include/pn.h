@@ -183,6 +183,15 @@ int pn_autotune(int64_t n, int64_t ld, const double* m, const double* S0, const 
                 double* dots, pn_opts* best, double* times_ms, void* stream);
 
 /*
+ * pn_shutdown -- frees the library's context on the current device (its
+ * call slots); the next call on that device creates it again.  Call it only
+ * when no work of the library is queued or running on the device, and not
+ * concurrently with other calls for that device.  PN_OK also when there is
+ * no context; PN_EHIP if freeing failed.
+ */
+int pn_shutdown(void);
+
+/*
  * pn_fma_rate -- the device's sustained vector multiply-add rate, the
  * measured counterpart of the datasheet peaks that roofline fractions are
  * quoted against: eight independent FMA chains per lane, 16 x iters steps

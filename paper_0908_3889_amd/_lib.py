@@ -28,7 +28,7 @@ EXPORTS = ("pn_integrate", "pn_rhs", "pn_observables", "pn_strerror", "pn_versio
            "pn_tape_stride", "pn_integrate_record", "pn_adjoint_workspace_bytes",
            "pn_integrate_adjoint", "pn_histogram", "pn_histogram2d", "pn_pearson", "pn_kde",
            "pn_ks_workspace_bytes", "pn_ks_uniform", "pn_stats_workspace_bytes", "pn_generate",
-           "pn_autotune", "pn_integrate_phase", "pn_fma_rate")
+           "pn_autotune", "pn_integrate_phase", "pn_fma_rate", "pn_shutdown")
 
 
 class PnOpts(C.Structure):
@@ -77,6 +77,8 @@ def load():
     L.pn_integrate_phase.restype = C.c_int
     L.pn_fma_rate.argtypes = [C.c_int32, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double), vp]
     L.pn_fma_rate.restype = C.c_int
+    L.pn_shutdown.argtypes = []
+    L.pn_shutdown.restype = C.c_int
     L.pn_rhs.argtypes = [i64, i64, vp, vp, vp, popts, vp]
     L.pn_rhs.restype = C.c_int
     L.pn_observables.argtypes = [i64, i64, vp, vp, vp]

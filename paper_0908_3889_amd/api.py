@@ -255,6 +255,12 @@ class PNIntegrate(torch.autograd.Function):
         return g["m"], g["S0"], g["L0"], g["omega0"], None, None, None, None
 
 
+def pn_shutdown() -> None:
+    """Free the library's context on the current device (call slots); only
+    when none of its work is pending (synchronize first)."""
+    check(load().pn_shutdown(), "pn_shutdown")
+
+
 def pn_fma_rate(waves_per_simd: int = 8, iters: int = 4000, stream=None) -> dict:
     """Sustained vector FMA rate of the current device in TFLOP/s: FP32
     without packed instructions, and FP64 (blocks until measured)."""

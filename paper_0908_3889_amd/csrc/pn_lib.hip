@@ -1148,6 +1148,18 @@ int get_ctx(DevCtx** out) {
     return PN_OK;
 }
 
+int release_ctx() {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return PN_ENODEV;
+    std::lock_guard<std::mutex> lk(g_ctx_mu);
+    DevCtx& c = g_ctx[dev];
+    if (!c.ready.load(std::memory_order_relaxed)) return PN_OK;
+    c.ready.store(false, std::memory_order_release);
+    const hipError_t e = hipFree(c.counters);
+    c.counters = nullptr;
+    return e == hipSuccess ? PN_OK : PN_EHIP;
+}
+
 TermConsts term_consts(int terms) {
     TermConsts tc;
     const bool pn_on = (terms & PN_TERM_PN) != 0;
@@ -1224,6 +1236,8 @@ const char* pn_strerror(int code) {
 }
 
 const char* pn_version(void) { return "pn-gfx950 0.2"; }
+
+int pn_shutdown(void) { return release_ctx(); }
 
 static int integrate_impl(int64_t n, int64_t ld, const double* m, const double* S0, const double* L0,
                           const double* omega0, double omega_f, double tol, const pn_opts* opt,

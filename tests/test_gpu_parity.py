@@ -306,3 +306,15 @@ def test_full_size_sampled_parity(workload, sample):
     n1 = np.linalg.norm(rg["y"][1:4], axis=0) / np.maximum(np.linalg.norm(pop["S"][:3], axis=0), 1e-300)
     assert np.abs(np.linalg.norm(rg["y"][7:], axis=0) - 1).max() < 1e-5
     assert np.abs(n1 - 1)[np.linalg.norm(pop["S"][:3], axis=0) > 1e-3].max() < 1e-3
+
+
+def test_shutdown_releases_and_the_next_call_recreates_the_context():
+    from paper_0908_3889_amd import api
+    pop = P.generate("adjoint_64k", 333)
+    a = run_gpu(pop)
+    torch.cuda.synchronize()
+    api.pn_shutdown()
+    api.pn_shutdown()                      # nothing left to free: still fine
+    b = run_gpu(pop)
+    for k in ("y", "t", "steps", "status", "dots"):
+        np.testing.assert_array_equal(a[k], b[k])
