@@ -113,7 +113,8 @@ def generate(w: Workload | str, n: int | None = None) -> dict:
     """Draw the population of workload `w` (optionally only its first n).
 
     The draw is always made at the workload's full size (or at n, if larger)
-    and then cut, so the first n inspirals are the same whatever n is.
+    and then cut, so the first n inspirals are the same for every n up to the
+    workload's size; a larger n is a different draw.
     """
     if isinstance(w, str):
         w = WORKLOADS[w]
