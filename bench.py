@@ -478,7 +478,7 @@ def main() -> int:
     if not args.no_cpu_baseline:
         gpu = {"dots": out["dots"].cpu().numpy(), "steps": steps, "status": status}
         # FP32-split is checked against the FP64 oracle with its own error bound
-        res["cpu_baseline"] = cpu_baseline(pop, args.cpu_budget, gpu, 1e-8 if precision == "fp64" else 2e-4)
+        res["cpu_baseline"] = cpu_baseline(pop, args.cpu_budget, gpu, 1e-8 if precision == "fp64" else 1e-3)
     print(json.dumps(res), flush=True)
     return 0
 
