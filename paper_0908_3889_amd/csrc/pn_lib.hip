@@ -843,7 +843,9 @@ __device__ __forceinline__ void replay_step(const Row& R, const TermConsts& tc, 
 //       ms[(j * 10 + c) * 64], j = 0..4 for mu_2..mu_6.
 __device__ __forceinline__ void reverse_step(const Row& R, const TermConsts& tc, double h, bool om, bool last,
                                              double* lam, double lt, RowBar& rb, double* __restrict__ ys,
-                                             int64_t ystride, double* __restrict__ ms) {
+                                             int64_t ystride, double* __restrict__ ms,
+                                             const double* __restrict__ pf, int64_t pfstride,
+                                             double* __restrict__ nx) {
 #define YS(S, C) ys[((S) * 10 + (C)) * ystride]
 #if PN_ADJ_MU_LDS
 #define MS(J, C) ms[((J) * 10 + (C)) * 64]
@@ -857,6 +859,12 @@ __device__ __forceinline__ void reverse_step(const Row& R, const TermConsts& tc,
         double y[10];
 #pragma unroll
         for (int c = 0; c < 10; ++c) y[c] = YS(0, c);
+        // the next reverse step's state and step size: loaded now, stored to
+        // LDS once the stage points are formed, so that the load latency
+        // overlaps the recomputation instead of opening the next step
+        double nxt[11];
+#pragma unroll
+        for (int c = 0; c < 11; ++c) nxt[c] = pf[c * pfstride];
         if (PN_ADJ_BASE) lb = log_base(R, y);
         double k1[10], k2[10], k3[10], k4[10], k5[10], Y[10];
         stage_deriv(R, tc, lb, y, k1, om);
@@ -892,6 +900,9 @@ __device__ __forceinline__ void reverse_step(const Row& R, const TermConsts& tc,
             YS(5, c) = __builtin_fma(h * A65, k5[c], __builtin_fma(h * A64, k4[c],
                        __builtin_fma(h * A63, k3[c], __builtin_fma(h * A62, k2[c],
                        __builtin_fma(h * A61, k1[c], y[c])))));
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int c = 0; c < 11; ++c) nx[c * 64] = nxt[c];
     }
 
     // reverse: stage i = 6 .. 1; mu_j (j > i) read back from LDS
@@ -947,7 +958,7 @@ __device__ __forceinline__ void reverse_step(const Row& R, const TermConsts& tc,
 // wsl[(k * 11 + c) * n] (c < 10: the state before step k of the segment,
 // c = 10: that step's size), so that a wave's accesses are coalesced.
 __device__ void adjoint_one(const AdjIo& io, const AdjUni& u, int64_t idx, double* wsl, double* ys,
-                            int64_t ystride, double* ms) {
+                            int64_t ystride, double* ms, double* nx) {
     const int64_t ld = u.ld;
     const int st = io.status[idx];
     const double* tp = u.tape + idx * u.tape_stride;
@@ -1005,21 +1016,32 @@ __device__ void adjoint_one(const AdjIo& io, const AdjUni& u, int64_t idx, doubl
         double y[10];
 #pragma unroll
         for (int c = 0; c < 10; ++c) y[c] = ck[(int64_t)sg * 10 + c];
+        double hk = hs[k0];
         for (int k = k0; k < k1; ++k) {
             const bool om = k >= nt;
-            const double h = (om && k == N - 1) ? u.omega_f - y[0] : hs[k];
+            const double h = (om && k == N - 1) ? u.omega_f - y[0] : hk;
+            if (k + 1 < k1) {
+                hk = hs[k + 1];                   // loaded a step ahead
 #pragma unroll
-            for (int c = 0; c < 10; ++c) WS(k - k0, c) = y[c];
-            WS(k - k0, 10) = h;
-            if (k + 1 < k1) replay_step(R, u.tc, y, h, om);   // the state after the segment is not needed
+                for (int c = 0; c < 10; ++c) WS(k - k0, c) = y[c];
+                WS(k - k0, 10) = h;
+                replay_step(R, u.tc, y, h, om);   // the state after the segment is not needed
+            } else {
+                // the segment's last step is reversed first: straight to LDS
+#pragma unroll
+                for (int c = 0; c < 10; ++c) nx[c * 64] = y[c];
+                nx[10 * 64] = h;
+            }
         }
         for (int k = k1 - 1; k >= k0; --k) {
 #pragma unroll
-            for (int c = 0; c < 10; ++c) ys[c * ystride] = WS(k - k0, c);
-            const double h = WS(k - k0, 10);
+            for (int c = 0; c < 10; ++c) ys[c * ystride] = nx[c * 64];
+            const double h = nx[10 * 64];
             const bool om = k >= nt;
             const bool last = om && k == N - 1;
-            reverse_step(R, u.tc, h, om, last, lam, lt, rb, ys, ystride, ms);
+            // the step reversed next (k - 1; at k0 a valid row, not used)
+            const double* pf = &WS((k > k0 ? k - 1 : k0) - k0, 0);
+            reverse_step(R, u.tc, h, om, last, lam, lt, rb, ys, ystride, ms, pf, wstride, nx);
         }
     }
 #undef WS
@@ -1056,6 +1078,8 @@ __global__ __launch_bounds__(BLOCK) void adjoint_kernel(AdjIo io, AdjUni u) {
     double* ys = &s_ys[threadIdx.x / 64][0][lane_id()];
     const int64_t ystride = 64;
 #endif
+    __shared__ double s_nx[BLOCK / 64][11][64];     // state and step size of the step reversed next
+    double* nx = &s_nx[threadIdx.x / 64][0][lane_id()];
     const int64_t j = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
     if (j >= u.n) return;
     const int64_t idx = io.order ? (int64_t)io.order[j] : j;
@@ -1065,7 +1089,7 @@ __global__ __launch_bounds__(BLOCK) void adjoint_kernel(AdjIo io, AdjUni u) {
     double* ys = io.ystage + j;
     const int64_t ystride = u.n;
 #endif
-    adjoint_one(io, u, idx, io.ws + j, ys, ystride, ms);
+    adjoint_one(io, u, idx, io.ws + j, ys, ystride, ms, nx);
 }
 
 // Zeroes the work counter of a persistent launch and writes its launch
