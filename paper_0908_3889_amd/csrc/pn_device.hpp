@@ -250,7 +250,7 @@ struct LogBase {
 };
 
 // dy/dt of Eqs. (1)-(4) at y = (w, S1, S2, L) into d (d omega/dt in d[0]);
-// returns ln|M w| as used.
+// returns ln|M w| as used, and x = (M w)^{1/3} as used in xo.
 //
 // With v = M w and x = v^{1/3}:
 //   d w/dt = K w^2 x^5 B,  B = 1 + x^2 (c2 + x (c3' + x (c4' + x (c5 + x (c6' + x c7)))))
@@ -266,8 +266,8 @@ struct LogBase {
 // be negative; x is then the real cube root and the log term uses
 // ln(16 x^2) = ln 16 + (2/3) ln|v|, which is what Eq. (1) gives for any real x.
 template <class RowT, bool FAST_LOG>
-__device__ __forceinline__ double rhs(const RowT& r, const TermConsts& tc, const LogBase& lb,
-                                      const double* __restrict__ y, double* __restrict__ d) {
+__device__ __forceinline__ double rhs_x(const RowT& r, const TermConsts& tc, const LogBase& lb,
+                                        const double* __restrict__ y, double* __restrict__ d, double& xo) {
     const double w = y[0];
     const double v = r[R_M] * w;
     double x, lnv;
@@ -323,7 +323,15 @@ __device__ __forceinline__ double rhs(const RowT& r, const TermConsts& tc, const
     d[7] = q * (d[1] + d[4]);
     d[8] = q * (d[2] + d[5]);
     d[9] = q * (d[3] + d[6]);
+    xo = x;
     return lnv;
+}
+
+template <class RowT, bool FAST_LOG>
+__device__ __forceinline__ double rhs(const RowT& r, const TermConsts& tc, const LogBase& lb,
+                                      const double* __restrict__ y, double* __restrict__ d) {
+    double x;
+    return rhs_x<RowT, FAST_LOG>(r, tc, lb, y, d, x);
 }
 
 // the base of the stage logs at the state y

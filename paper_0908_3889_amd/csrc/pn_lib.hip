@@ -289,6 +289,7 @@ struct LaneF64 {
     double y[10];
     double k1[10];
     double lnv;       // ln|M omega| at y, carried from the stage that produced y
+    double x;         // (M omega)^{1/3} at y, carried likewise
     double dt1;       // dt/d(variable) of k1: 1 in time mode, 1/omega-dot in omega mode
     double t, h;
     double phase;     // integral of omega dt (phase kernels only)
@@ -318,7 +319,7 @@ struct F64 {
         L.phase = 0.0;
         make_row(L.row, m1, m2, u.terms, u.theta_literal);
         LogBase lb;
-        L.lnv = rhs<Row, false>(L.row, u.tc, lb, L.y, L.k1);
+        L.lnv = rhs_x<Row, false>(L.row, u.tc, lb, L.y, L.k1, L.x);
         L.dt1 = 1.0;
         L.nrhs = 1;
         L.nt = 0;
@@ -359,7 +360,7 @@ struct F64 {
         lb.w = y[0];
         lb.iw = rcp_pos(y[0]);
         lb.lnv = L.lnv;
-        lb.x = cbrt_real(R[R_M] * y[0]);
+        lb.x = L.x;
         {
             const double c1 = h * A21;
 #pragma unroll
@@ -417,8 +418,8 @@ struct F64 {
                         __builtin_fma(E3, k3[c], E1 * k1[c]))));
             }
         }
-        double k7[10], dt7 = 1.0;
-        const double lnv7 = rhs<Row, true>(R, u.tc, lb, Y, k7);
+        double k7[10], dt7 = 1.0, x7;
+        const double lnv7 = rhs_x<Row, true>(R, u.tc, lb, Y, k7, x7);
         if (any_w) to_omega_variable(k7, dt7, L.omega_mode);
         L.nrhs += go ? 6 : 0;
 
@@ -434,6 +435,7 @@ struct F64 {
         const int acc0 = L.acc;
         const int r = control<RECORD, GEN>(u, L, go, st0, fin, z, h, last, Y, k7, dt7, dts);
         L.lnv = L.acc != acc0 ? lnv7 : L.lnv;
+        L.x = L.acc != acc0 ? x7 : L.x;
         if (PHASE) L.phase = L.acc != acc0 ? __builtin_fma(h, ps, L.phase) : L.phase;
         return r;
     }
