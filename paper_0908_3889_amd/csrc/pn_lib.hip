@@ -166,7 +166,9 @@ __device__ int read_input(const Io& io, const Uni& u, int64_t idx, double* y, do
     return 0;
 }
 
-// error norm z = err^2 = mean_c (e_c / (tol + tol max(|y_c|, |ynew_c|)))^2
+// mean_c (e_c / (tol + tol max(|y_c|, |ynew_c|)))^2: the squared RMS error norm
+// z = err^2 of the error estimate e (the FP64 stepper passes e/h and scales
+// the result by h^2)
 __device__ __forceinline__ double error_norm(const Uni& u, const double* y, const double* ynew, const double* e) {
     double z = 0.0;
 #pragma unroll
@@ -425,10 +427,11 @@ struct F64 {
 
         // the error norm is formed in fixed-step mode too (and ignored there),
         // which keeps it in the same block as its operands
+        // the error estimate is h e'; its norm is formed from e' and scaled by h^2
         double e[10];
 #pragma unroll
-        for (int c = 0; c < 10; ++c) e[c] = h * __builtin_fma(E7, k7[c], Ep[c]);
-        const double z = error_norm(u, y, Y, e);
+        for (int c = 0; c < 10; ++c) e[c] = __builtin_fma(E7, k7[c], Ep[c]);
+        const double z = error_norm(u, y, Y, e) * (h * h);
         bool fin = (GEN && u.fixed) || !__builtin_isnan(z);
 #pragma unroll
         for (int c = 0; c < 10; ++c) fin = fin && finite(Y[c]);
