@@ -209,7 +209,7 @@ __device__ __forceinline__ void make_row(RowT& r, double m1, double m2, int term
 // series 2 (s + s^3/3 + ... + s^11/11) (relative remainder < 2e-16).
 __device__ __forceinline__ double log1p_small(double u) {
     const double d = 2.0 + u;
-    const double rd = rcp_pos(d);
+    const double rd = rcp_1step(d);     // the residual correction below restores s to rounding
     double s = u * rd;
     s = __builtin_fma(__builtin_fma(-s, d, u), rd, s);
     const double s2 = s * s;
@@ -253,12 +253,13 @@ struct LogBase {
 // returns ln|M w| as used, and x = (M w)^{1/3} as used in xo.
 //
 // With v = M w and x = v^{1/3}:
-//   d w/dt = K w^2 x^5 B,  B = 1 + x^2 (c2 + x (c3' + x (c4' + x (c5 + x (c6' + x c7)))))
+//   d w/dt = K w^2 x^5 B (formed as K w^2 x^2 v B),
+//     B = 1 + x^2 (c2 + x (c3' + x (c4' + x (c5 + x (c6' + x c7)))))
 //     c3' = 4 pi - so1 L.S1 - so2 L.S2,
 //     c4' = c4 - ssd (247 S1.S2 - 721 (L.S1)(L.S2)),
 //     c6' = c6 - (1712/105) ln x;
-//   Omega_1 x S1 = p [ (g1 x^2 - 3 sv L.S2) (L x S1) - sv (S1 x S2) ],
-//   Omega_2 x S2 = p [ (g2 x^2 - 3 sv L.S1) (L x S2) + sv (S1 x S2) ],
+//   dS1/dt = Omega_1 x S1,  Omega_1 = p [ (g1 x^2 - 3 sv L.S2) L + sv S2 ],
+//   dS2/dt = Omega_2 x S2,  Omega_2 = p [ (g2 x^2 - 3 sv L.S1) L + sv S1 ],
 //     p = w/2 = (M w)/(2M),  sv = w/M  (Eq. (4) expanded; the eta (M w)^{-1/3}
 //     term times (M w)^2/(2M) is p g_i x^2);
 //   dL/dt = -lam x (dS1/dt + dS2/dt)   (Eq. (3)).
@@ -298,27 +299,25 @@ __device__ __forceinline__ double rhs_x(const RowT& r, const TermConsts& tc, con
     B = __builtin_fma(x, B, c3p);
     B = __builtin_fma(x, B, r[R_C2]);
     B = __builtin_fma(x2, B, 1.0);
-    const double x5 = x2 * x2 * x;
-    d[0] = (r[R_K] * (w * w)) * x5 * B;
+    // x^5 = x^2 v (x^3 = v)
+    d[0] = (r[R_K] * (w * w)) * (x2 * v) * B;
 
     const double p = 0.5 * w;
     const double sv = r[R_SIGM] * w;
     const double al1 = p * __builtin_fma(r[R_G1], x2, -3.0 * sv * LS2);
     const double al2 = p * __builtin_fma(r[R_G2], x2, -3.0 * sv * LS1);
     const double be = p * sv;
-    // L x S1, L x S2, S1 x S2
-    const double u0 = __builtin_fma(L1, a2, -L2 * a1), u1 = __builtin_fma(L2, a0, -L0 * a2),
-                 u2 = __builtin_fma(L0, a1, -L1 * a0);
-    const double w0 = __builtin_fma(L1, b2, -L2 * b1), w1 = __builtin_fma(L2, b0, -L0 * b2),
-                 w2 = __builtin_fma(L0, b1, -L1 * b0);
-    const double c0 = __builtin_fma(a1, b2, -a2 * b1), c1 = __builtin_fma(a2, b0, -a0 * b2),
-                 cc2 = __builtin_fma(a0, b1, -a1 * b0);
-    d[1] = __builtin_fma(al1, u0, -be * c0);
-    d[2] = __builtin_fma(al1, u1, -be * c1);
-    d[3] = __builtin_fma(al1, u2, -be * cc2);
-    d[4] = __builtin_fma(al2, w0, be * c0);
-    d[5] = __builtin_fma(al2, w1, be * c1);
-    d[6] = __builtin_fma(al2, w2, be * cc2);
+    // Omega_1 = al1 L + be S2, Omega_2 = al2 L + be S1
+    const double o0 = __builtin_fma(al1, L0, be * b0), o1 = __builtin_fma(al1, L1, be * b1),
+                 o2 = __builtin_fma(al1, L2, be * b2);
+    const double g0 = __builtin_fma(al2, L0, be * a0), g1 = __builtin_fma(al2, L1, be * a1),
+                 g2 = __builtin_fma(al2, L2, be * a2);
+    d[1] = __builtin_fma(o1, a2, -o2 * a1);
+    d[2] = __builtin_fma(o2, a0, -o0 * a2);
+    d[3] = __builtin_fma(o0, a1, -o1 * a0);
+    d[4] = __builtin_fma(g1, b2, -g2 * b1);
+    d[5] = __builtin_fma(g2, b0, -g0 * b2);
+    d[6] = __builtin_fma(g0, b1, -g1 * b0);
     const double q = -r[R_LAM] * x;
     d[7] = q * (d[1] + d[4]);
     d[8] = q * (d[2] + d[5]);
@@ -400,25 +399,23 @@ __device__ __forceinline__ void rhs_f32(const RowF& r, const TermConstsF& tc, co
     B = __builtin_fmaf(x, B, c3p);
     B = __builtin_fmaf(x, B, r[R_C2]);
     B = __builtin_fmaf(x2, B, 1.0f);
-    const float x5 = x2 * x2 * x;
-    d[0] = (r[R_K] * (w * w)) * x5 * B;
+    d[0] = (r[R_K] * (w * w)) * (x2 * v) * B;     // x^5 = x^2 v
     const float p = 0.5f * w;
     const float sv = r[R_SIGM] * w;
     const float al1 = p * __builtin_fmaf(r[R_G1], x2, -3.0f * sv * LS2);
     const float al2 = p * __builtin_fmaf(r[R_G2], x2, -3.0f * sv * LS1);
     const float be = p * sv;
-    const float u0 = __builtin_fmaf(L1, a2, -L2 * a1), u1 = __builtin_fmaf(L2, a0, -L0 * a2),
-                u2 = __builtin_fmaf(L0, a1, -L1 * a0);
-    const float w0 = __builtin_fmaf(L1, b2, -L2 * b1), w1 = __builtin_fmaf(L2, b0, -L0 * b2),
-                w2 = __builtin_fmaf(L0, b1, -L1 * b0);
-    const float c0 = __builtin_fmaf(a1, b2, -a2 * b1), c1 = __builtin_fmaf(a2, b0, -a0 * b2),
-                cc2 = __builtin_fmaf(a0, b1, -a1 * b0);
-    d[1] = __builtin_fmaf(al1, u0, -be * c0);
-    d[2] = __builtin_fmaf(al1, u1, -be * c1);
-    d[3] = __builtin_fmaf(al1, u2, -be * cc2);
-    d[4] = __builtin_fmaf(al2, w0, be * c0);
-    d[5] = __builtin_fmaf(al2, w1, be * c1);
-    d[6] = __builtin_fmaf(al2, w2, be * cc2);
+    // Omega_1 = al1 L + be S2, Omega_2 = al2 L + be S1
+    const float o0 = __builtin_fmaf(al1, L0, be * b0), o1 = __builtin_fmaf(al1, L1, be * b1),
+                o2 = __builtin_fmaf(al1, L2, be * b2);
+    const float g0 = __builtin_fmaf(al2, L0, be * a0), g1 = __builtin_fmaf(al2, L1, be * a1),
+                g2 = __builtin_fmaf(al2, L2, be * a2);
+    d[1] = __builtin_fmaf(o1, a2, -o2 * a1);
+    d[2] = __builtin_fmaf(o2, a0, -o0 * a2);
+    d[3] = __builtin_fmaf(o0, a1, -o1 * a0);
+    d[4] = __builtin_fmaf(g1, b2, -g2 * b1);
+    d[5] = __builtin_fmaf(g2, b0, -g0 * b2);
+    d[6] = __builtin_fmaf(g0, b1, -g1 * b0);
     const float q = -r[R_LAM] * x;
     d[7] = q * (d[1] + d[4]);
     d[8] = q * (d[2] + d[5]);
