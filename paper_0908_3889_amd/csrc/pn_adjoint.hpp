@@ -231,7 +231,10 @@ __device__ __forceinline__ void rhs_vjp(const Row& r, const TermConsts& tc, cons
     bb2 = __builtin_fma(L2, LS2bar, __builtin_fma(a2, S12bar, bb2));
     // x2 = x x ; lnv = ln|v| ; x = cbrt(v) ; v = M w
     xbar = __builtin_fma(2.0 * x, x2bar, xbar);
-    const double vbar = lnvbar / v + xbar / (3.0 * x2);
+    // d lnv/dv = 1/v, dx/dv = 1/(3 x^2) = x/(3 v): one reciprocal of v
+    // (hardware seed and two Newton steps; valid for either sign)
+    const double rv = rcp_pos(v);
+    const double vbar = rv * __builtin_fma(xbar, x * (1.0 / 3.0), lnvbar);
     rb.v[R_M] = __builtin_fma(w, vbar, rb.v[R_M]);
     wbar = __builtin_fma(M, vbar, wbar);
 

@@ -60,7 +60,8 @@ __device__ __forceinline__ double cbrt_real(double v) {
     return __builtin_copysign(x, v);
 }
 
-// 1/d for d > 0 normal: hardware reciprocal refined by two Newton steps.
+// 1/d for d normal (either sign; the name records the callers' usual case):
+// hardware reciprocal refined by two Newton steps.
 __device__ __forceinline__ double rcp_pos(double d) {
     double r = __builtin_amdgcn_rcp(d);
     double e = __builtin_fma(-d, r, 1.0);
