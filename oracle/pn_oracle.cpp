@@ -53,10 +53,20 @@
  *   R21 the orbital phase (not a quantity of the paper) is the integral of
  *       omega dt from 0, taken on the accepted steps as described above.
  *
- * Parity unpinned: the paper prints no trajectory, no step count and no
- * controller constants, so the step sequence itself (R7, R8, R10) is pinned
- * only by the convergence, closed-form and invariant checks of the tests and
- * by the paper's printed correlation coefficients (Sec. V A).
+ * Pins of the step sequence: the paper prints no trajectory, no step count
+ * and no controller constants.  The error norm and the controller (R7, R8)
+ * are pinned by SciPy's RK45, an independent implementation of the same
+ * pair and controller, whose accepted time steps and rejections the tests
+ * compare with these.  Parity unpinned: the omega stretch (R10), which is
+ * pinned only through convergence to closed forms and to an event-located
+ * library integration, and the paper's printed correlation coefficients
+ * (Sec. V A).
+ *
+ * The stage sums skip the tableau's structural zeros (a_sj = 0, and
+ * b_j = bhat_j = 0 in the error estimate): the method's sums run over the
+ * nonzero weights only, so a stage derivative that is infinite where its
+ * weight is structurally zero must not turn the sum into 0 * inf = NaN,
+ * and the operation counts of the counting scalar are the method's.
  *
  * Build: g++ -O2 -std=c++17 -fno-fast-math -ffp-contract=off -shared -fPIC.
  */

@@ -313,6 +313,82 @@ def test_against_scipy_dop853_with_terminal_event():
 
 
 # ---------------------------------------------------------------------------
+# Step controller: SciPy's RK45, an independent implementation of the same
+# Dormand-Prince pair and the same controller
+# ---------------------------------------------------------------------------
+
+def _scipy_rk45_t_stretch(m, y0, tol, omega_f, h0):
+    """Accepted step sizes of scipy.integrate.RK45 from y0 (first step h0,
+    rtol = atol = tol) up to its first step that passes omega_f, and the
+    rejections before that step's acceptance (each attempt costs six
+    right-hand-side evaluations)."""
+    calls = [0]
+
+    def f(t, y):
+        calls[0] += 1
+        return oracle.rhs(m, y.reshape(10, 1))[:, 0]
+
+    s = si.RK45(f, 0.0, y0, t_bound=1e12, first_step=h0, rtol=tol, atol=tol)
+    hs, rej = [], 0
+    while True:
+        c0 = calls[0]
+        assert s.step() is None and s.status == "running"
+        attempts, left = divmod(calls[0] - c0, 6)
+        assert left == 0
+        rej += attempts - 1
+        if s.y[0] > omega_f:
+            return np.array(hs), rej
+        hs.append(s.h_previous)
+
+
+@pytest.mark.parametrize("workload,h0", [("q1to4_1M", 10.0), ("equal_mass_maxspin_1k", 10.0),
+                                         ("q1to4_1M", 2e4)])
+def test_step_controller_matches_scipy_rk45(monkeypatch, workload, h0):
+    """SciPy's RK45 is the Dormand-Prince 5(4) pair advancing with the
+    5th-order solution, with the root-mean-square error norm over the
+    components scaled by atol + rtol max(|y|, |y_new|), safety factor 0.9,
+    exponent -1/5, smallest factor 0.2 and no growth right after a
+    rejection: readings R7 and R8 of Sec. II's "error tolerance".  Its
+    largest growth factor is 10 where R8 reads 5; patched to 5, with the
+    initial step h = 10 of Sec. II and rtol = atol = tol, its accepted time
+    steps up to the step that passes omega_f must be the oracle's, with the
+    same rejections.  A first step of 2e4 is rejected by factors of the
+    smallest factor, so that clamp is exercised too.
+
+    The step sizes agree to rounding of the error estimate, which is a
+    small difference of stage derivatives (at tol = 1e-10 about 1e-7 of
+    them), so a different summation order moves the error norm by up to
+    ~1e-7 relative and the next step by a fifth of that: measured at most
+    3.2e-8 (median 5e-10) over these workloads.  A wrong exponent (-1/4),
+    safety factor (0.95), clamp (10 or 0.1) or norm (a max-norm) moves the
+    steps by 0.6 % to 300 % and changes the step counts."""
+    import scipy.integrate._ivp.rk as rk
+    monkeypatch.setattr(rk, "MAX_FACTOR", 5.0)
+    pop = P.generate(workload, 8)
+    r = oracle.integrate(pop["m"], pop["S"], pop["L"], pop["omega0"], pop["omega_f"], pop["tol"],
+                         h0=h0, record=8192, nthreads=NT)
+    assert (r["status"] == 0).all()
+    n_t, n_w = r["n_tw"]
+    rels = []
+    for i in range(pop["n"]):
+        y0 = np.concatenate([[pop["omega0"][i]], pop["S"][:, i], pop["L"][:, i]])
+        hs, rej = _scipy_rk45_t_stretch(pop["m"][:, i:i + 1], y0, pop["tol"], pop["omega_f"], h0)
+        assert hs.size == n_t[i]
+        rels.append(np.abs(hs / r["h_record"][i, :n_t[i]] - 1))
+        # an omega stretch of one step had no rejection, so all of the
+        # oracle's rejections are in the time stretch
+        if n_w[i] == 1:
+            assert rej == r["steps"][1][i]
+        else:
+            assert rej <= r["steps"][1][i]
+    rel = np.concatenate(rels)
+    assert rel.max() < 1e-7 and np.median(rel) < 1e-9, (rel.max(), np.median(rel))
+    assert (n_w == 1).sum() >= pop["n"] // 2
+    if h0 > 10.0:
+        assert r["steps"][1].min() >= 2         # the first step is rejected by the smallest factor
+
+
+# ---------------------------------------------------------------------------
 # Termination and status codes
 # ---------------------------------------------------------------------------
 
