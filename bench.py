@@ -28,12 +28,40 @@ if ROOT not in sys.path:
 
 METRIC = "inspirals/s to ω_f at 1e-8 tol; RHS evals/s as % VALU peak; adjoint/fwd cost"
 
-# Algorithmic work per unit, counted on the oracle with a scalar type that
-# counts the state-dependent add/sub/mul/div (cube root and log not counted):
-# one right-hand-side evaluation of Eqs. (1)-(4), and the stage sums, error
-# estimate, error norm and step control of one attempted step.
-F_RHS = 134
-F_STEP_COMB = 704
+# Algorithmic work per unit: the arithmetic of Eqs. (1)-(4) and of the
+# Dormand-Prince tableau with each operation written once, a fused
+# multiply-add counted as 2 FLOP and a division as 1; the cube root, the log
+# and err^(-1/5) are special functions and not counted.  One right-hand-side
+# evaluation (F_RHS) and the stage sums, error estimate, error norm and step
+# control of one attempted step (F_STEP_COMB).  RHS_FLOP and COMB_FLOP list
+# the terms; tests check that they add up.
+RHS_FLOP = {
+    "v = M w, x^2": 2,
+    "L.S1, L.S2, S1.S2 (2 FMA + 1 MUL each)": 15,
+    "3.5PN bracket: spin-orbit (2 FMA), spin-spin (2 MUL + FMA), c4', c6' (FMA each)": 12,
+    "Horner chain in x (6 FMA)": 12,
+    "d omega/dt = K w^2 x^2 v B (5 MUL)": 5,
+    "p = w/2, s_v = w/M, -3 s_v": 3,
+    "alpha_1, alpha_2 (MUL + FMA + MUL each), beta": 9,
+    "Omega_1, Omega_2 (3 MUL + 3 FMA each)": 18,
+    "Omega_1 x S1, Omega_2 x S2 (3 MUL + 3 FMA each)": 18,
+    "dL/dt = -lambda x (dS1 + dS2) (MUL, 3 ADD, 3 MUL)": 7,
+}
+COMB_FLOP = {
+    "stage points Y_2..Y_7: 20 nonzero a_sj x 10 components (FMA)": 400,
+    "h a_sj products": 20,
+    "error estimate sum_j (b_j - bhat_j) k_j: 10 x (MUL + 5 FMA)": 110,
+    "error norm: 10 x (scale FMA, division, square-add FMA), x 0.1 h^2": 53,
+    "step factor 0.9 p, h fac, t + h": 3,
+}
+F_RHS = sum(RHS_FLOP.values())            # 101
+F_STEP_COMB = sum(COMB_FLOP.values())     # 586
+# The oracle's own counts (its counting scalar: every add, sub, mul and div of
+# its deliberately plain association, one FLOP each) and the per-attempted-step
+# estimate of the hot-path plan, reported beside the fraction for comparison.
+ORACLE_F_RHS = 134
+ORACLE_F_STEP_COMB = 704
+PLAN_F_STEP = 1300
 FP64_VECTOR_PEAK_TFLOPS = 78.6      # MI355X: 256 CU x 2.4 GHz x 128 FLOP/clk
 FP32_VECTOR_PEAK_TFLOPS = 157.3     # MI355X datasheet (counts packed FP32; the library is
                                     # compiled without packed FP32 instructions, so half of
@@ -41,13 +69,17 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3     # MI355X datasheet (counts packed FP32; the 
 HBM_PEAK_GBS = 8000.0
 
 
-def algorithmic_flops(steps: np.ndarray) -> float:
+def algorithmic_flops(steps: np.ndarray, f_rhs: int = F_RHS, f_comb: int = F_STEP_COMB) -> float:
     """FLOPs of the method for step counts [3, n] (accepted, rejected, RHS evals):
     every attempted step costs 6 RHS evaluations + one combination; the first
     RHS evaluation of each inspiral is extra."""
     nrhs = steps[2].astype(np.int64)
     attempted = (nrhs - 1) // 6
-    return float((nrhs * F_RHS).sum() + (attempted * F_STEP_COMB).sum())
+    return float((nrhs * f_rhs).sum() + (attempted * f_comb).sum())
+
+
+def attempted_steps(steps: np.ndarray) -> int:
+    return int(((steps[2].astype(np.int64) - 1) // 6).sum())
 
 
 def cpu_baseline(pop: dict, budget_s: float = 12.0, gpu: dict | None = None, dot_tol: float = 1e-8) -> dict:
@@ -171,6 +203,140 @@ def _time(fn, steps, warmup, stream):
         b.record(stream)
     torch.cuda.synchronize()
     return float(np.mean([a.elapsed_time(b) for a, b in ev]))
+
+
+def _time_calls(fn, reps: int, stream) -> float:
+    """Mean time (ms) per call of `reps` back-to-back calls of fn, between two
+    HIP events on the launch stream (after one untimed call)."""
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(reps):
+        fn()
+    b.record(stream)
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def _frac(steps: np.ndarray, ms: float, peak: float) -> float:
+    return algorithmic_flops(steps) / (ms * 1e-3) / 1e12 / peak
+
+
+def _stats(x: np.ndarray) -> dict:
+    x = np.asarray(x, dtype=np.float64)
+    return {"max": float(x.max()), "p99": float(np.percentile(x, 99))}
+
+
+def leg_adjoint(api, population, stream, ks=(16, 64, 256), reps: int = 5, n: int | None = None) -> dict:
+    """The differentiation workload (65,536 inspirals, tol 1e-8): the plain
+    forward, the forward that records the tape (r_ckpt) and the discrete
+    adjoint of loss = sum S1.S2 + sum L_hat_z (r_bwd), per checkpoint
+    spacing K, each against the plain forward."""
+    import torch
+    w = population.WORKLOADS["adjoint_64k"]
+    pop = population.generate(w, n)
+    d = api.to_device(pop)
+    out = api.alloc_outputs(pop["n"])
+    fwd = lambda: api.pn_integrate(d["m"], d["S"], d["L"], d["omega0"], pop["omega_f"], pop["tol"], out=out,
+                                   stream=stream)
+    t_fwd = _time_calls(fwd, reps, stream)
+    res = {"workload": w.name, "n": pop["n"], "tol": w.tol, "loss": "sum S1.S2 + sum L_hat_z (final)",
+           "fwd_ms": t_fwd, "per_K": {},
+           "timing": f"HIP events around {reps} back-to-back calls on the launch stream"}
+    for K in ks:
+        box = {}
+
+        def rec():
+            box["rec"] = api.pn_integrate_record(d["m"], d["S"], d["L"], d["omega0"], pop["omega_f"],
+                                                 pop["tol"], cap_steps=1024, ckpt_every=K, stream=stream)
+        t_rec = _time_calls(rec, reps, stream)
+        r = box["rec"]
+        y = r["y"]
+        gy = torch.zeros_like(y)
+        gy[1:4] = y[4:7]
+        gy[4:7] = y[1:4]
+        gy[9] = 1.0
+        order = torch.argsort(r["steps"][0], descending=True).to(torch.int32)
+
+        def adj():
+            box["g"] = api.pn_integrate_adjoint(d["m"], pop["omega_f"], r, gy, order=order, stream=stream)
+        t_adj = _time_calls(adj, reps, stream)
+        res["per_K"][str(K)] = {"record_ms": t_rec, "adjoint_ms": t_adj, "r_ckpt": t_rec / t_fwd,
+                                "r_bwd": t_adj / t_fwd, "r_total": (t_rec + t_adj) / t_fwd,
+                                "ok": int((r["status"] == 0).sum().item()),
+                                "grad_finite": bool(torch.isfinite(box["g"]["S0"]).all().item())}
+    res["r_bwd_max"] = max(v["r_bwd"] for v in res["per_K"].values())
+    return res
+
+
+def leg_fp32split(api, pop, d, ref64: dict, stream, reps: int = 5) -> dict:
+    """FP32-split on the same population as the FP64 run: time, fraction of
+    the FP32 vector peak, and the error of every output against the FP64
+    path (which the CPU-baseline leg checks against the oracle)."""
+    import torch
+    opts = api.make_opts(precision="fp32split")
+    out = api.alloc_outputs(pop["n"])
+    run = lambda: api.pn_integrate(d["m"], d["S"], d["L"], d["omega0"], pop["omega_f"], pop["tol"], opts,
+                                   out=out, stream=stream)
+    ms = _time_calls(run, reps, stream)
+    g = {k: v.cpu().numpy() for k, v in out.items()}
+    ok = (g["status"] == 0) & (ref64["status"] == 0)
+    S0 = pop["S"]
+    n1 = np.linalg.norm(S0[:3], axis=0)
+    n2 = np.linalg.norm(S0[3:], axis=0)
+    n1[n1 == 0] = 1.0
+    n2[n2 == 0] = 1.0
+    y, y64 = g["y"][:, ok], ref64["y"][:, ok]
+    err = {
+        "S1h.S2h": _stats(np.abs(g["dots"][0] - ref64["dots"][0])[ok]),
+        "S1h.Lh": _stats(np.abs(g["dots"][1] - ref64["dots"][1])[ok]),
+        "S2h.Lh": _stats(np.abs(g["dots"][2] - ref64["dots"][2])[ok]),
+        "S1 (|dS1|/|S1(0)|)": _stats(np.linalg.norm(y[1:4] - y64[1:4], axis=0) / n1[ok]),
+        "S2 (|dS2|/|S2(0)|)": _stats(np.linalg.norm(y[4:7] - y64[4:7], axis=0) / n2[ok]),
+        "L_hat (|dL|)": _stats(np.linalg.norm(y[7:10] - y64[7:10], axis=0)),
+        "t (relative)": _stats(np.abs(g["t"][ok] / ref64["t"][ok] - 1)),
+    }
+    # the orbital phase, integrated alongside in both precisions (untimed)
+    p32 = api.pn_integrate_phase(d["m"], d["S"], d["L"], d["omega0"], pop["omega_f"], pop["tol"], opts,
+                                 stream=stream)
+    p64 = api.pn_integrate_phase(d["m"], d["S"], d["L"], d["omega0"], pop["omega_f"], pop["tol"],
+                                 stream=stream)
+    torch.cuda.synchronize()
+    ph32, ph64 = p32["phase"].cpu().numpy()[ok], p64["phase"].cpu().numpy()[ok]
+    err["phase (relative)"] = _stats(np.abs(ph32 / ph64 - 1))
+    return {"ms": ms, "frac": _frac(g["steps"], ms, FP32_VECTOR_PEAK_TFLOPS),
+            "frac_of_nonpacked_fp32": _frac(g["steps"], ms, FP32_VECTOR_PEAK_TFLOPS / 2),
+            "status_ok": int((g["status"] == 0).sum()), "n": pop["n"],
+            "steps_equal_to_fp64": float((g["steps"][:2] == ref64["steps"][:2]).all(axis=0).mean()),
+            "error_vs_fp64": err,
+            "reference": "the FP64 path on the whole population (its own distance from the oracle is "
+                         "cpu_baseline.crosscheck)"}
+
+
+def leg_batching(api, population, stream, reps: int = 3, n: int | None = None) -> dict:
+    """The batching workload (4,194,304 inspirals, omega0 log-uniform in
+    [0.002, 0.01], q in [1, 10]): the persistent refill kernel against one
+    lane per inspiral without refill."""
+    w = population.WORKLOADS["batching_4M"]
+    pop = population.generate(w, n)
+    d = api.to_device(pop)
+    out = api.alloc_outputs(pop["n"])
+    res = {"workload": w.name, "n": pop["n"]}
+    for sched in ("persistent", "static"):
+        opts = api.make_opts(schedule=sched)
+        run = lambda: api.pn_integrate(d["m"], d["S"], d["L"], d["omega0"], pop["omega_f"], pop["tol"], opts,
+                                       out=out, stream=stream)
+        ms = _time_calls(run, reps, stream)
+        steps = out["steps"].cpu().numpy()
+        res[sched] = {"ms": ms, "inspirals_per_s": pop["n"] / (ms * 1e-3),
+                      "frac": _frac(steps, ms, FP64_VECTOR_PEAK_TFLOPS),
+                      "status_ok": int((out["status"] == 0).sum().item())}
+    acc = steps[0].astype(np.int64)
+    res["accepted_steps_min_median_max"] = [int(acc.min()), int(np.median(acc)), int(acc.max())]
+    res["static_over_persistent"] = res["static"]["ms"] / res["persistent"]["ms"]
+    return res
 
 
 def bench_adjoint(args, api, pop, d, w, step, stream) -> int:
@@ -350,6 +516,8 @@ def main() -> int:
     ap.add_argument("--autotune", action="store_true",
                     help="choose refill threshold and block size with pn_autotune on a 2^20 sample first")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the adjoint, FP32-split and batching legs that follow the timed region")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     args = ap.parse_args()
 
@@ -446,14 +614,21 @@ def main() -> int:
                    "precision": precision, "schedule": args.schedule, "parallelism": "single GPU"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak,
                      "unit": "TFLOP/s", "frac": achieved / peak,
-                     "traffic": traffic},
+                     "traffic": traffic,
+                     "flop_per_unit": {"rhs_evaluation": F_RHS, "attempted_step_besides_rhs": F_STEP_COMB,
+                                       "launch": "sum over inspirals of RHS evaluations x F_rhs + "
+                                                 "attempted steps x F_comb"},
+                     "frac_at_oracle_count": algorithmic_flops(steps, ORACLE_F_RHS, ORACLE_F_STEP_COMB)
+                     / (avg_ms * 1e-3) / 1e12 / peak,
+                     "frac_at_1300_per_attempted_step": attempted_steps(steps) * PLAN_F_STEP
+                     / (avg_ms * 1e-3) / 1e12 / peak},
         "kernel": kernel,
         "kernel_resources": resources,
         "launch": {"block": opts.block or 256, "refill_min": opts.refill_min or 4,
                    "waves_per_simd": opts.waves_per_simd or None, "autotuned": tuned},
         "kernel_ms": avg_ms,
         "rhs_evals_per_s": float(steps[2].astype(np.int64).sum()) / (avg_ms * 1e-3),
-        "attempted_steps": int(((steps[2].astype(np.int64) - 1) // 6).sum()),
+        "attempted_steps": attempted_steps(steps),
         "accepted_steps": int(steps[0].astype(np.int64).sum()),
         "rejected_steps": int(steps[1].astype(np.int64).sum()),
         "algorithmic_flop_per_launch": flops,
@@ -475,6 +650,13 @@ def main() -> int:
             res["error_vs_fp64"]["phase_rel_p99"] = float(np.percentile(pr, 99))
     # the datasheet peak above, checked on this device (sustained FMA rate)
     res["vector_peak_probe"] = api.pn_fma_rate(8, 4000, stream=stream)
+    # the rest of the metric, after the timed region: the adjoint's cost, the
+    # FP32-split precision mode and the batching comparison
+    if not args.no_extras and w.name == "q1to4_1M" and precision == "fp64" and not args.phase:
+        ref64 = {k: v.cpu().numpy() for k, v in out.items() if v is not None}
+        res["adjoint"] = leg_adjoint(api, population, stream)
+        res["fp32split"] = leg_fp32split(api, pop, d, ref64, stream)
+        res["batching"] = leg_batching(api, population, stream)
     if not args.no_cpu_baseline:
         gpu = {"dots": out["dots"].cpu().numpy(), "steps": steps, "status": status}
         # FP32-split is checked against the FP64 oracle with its own error bound

@@ -31,11 +31,18 @@
  *    names a code.
  *  - Outcomes per inspiral go to status[i] (PN_ST_*), never to the return code.
  *  - Safe to call from several host threads on different streams.  The
- *    library keeps a small per-device context (1024 call slots of 512 bytes,
- *    each a work counter and the launch arguments of a persistent launch,
- *    and the device's compute-unit count), created on first use.  Calls
- *    take the slots in turn, so at most 1024 persistent launches may be in
- *    flight at once across all streams of a device.
+ *    library keeps a small per-device context, created on first use: the
+ *    device's compute-unit count and 5120 call slots of 512 bytes, each a
+ *    work counter and the launch arguments of one persistent launch (the
+ *    only device memory the library allocates).  Direct calls take the
+ *    first 1024 slots in turn; before a slot is reused, the new call's
+ *    stream waits for an event recorded after the launch that last used it,
+ *    so any number of launches may be queued on any streams.  A call made
+ *    while its stream is being captured into a HIP graph takes one of the
+ *    other 4096 slots for good (every replay of the graph uses it); when
+ *    those are used up such a call returns PN_EBUSY and launches nothing
+ *    (pn_shutdown frees them, and with them every graph captured before).
+ *    Replays of one graph must not overlap one another.
  */
 #ifndef PN_H
 #define PN_H
@@ -57,6 +64,7 @@ extern "C" {
 #define PN_ENODEV   -2   /* no usable device */
 #define PN_EHIP     -3   /* a HIP runtime call or kernel launch failed */
 #define PN_ENOMEM   -4   /* the library could not allocate its device context */
+#define PN_EBUSY    -5   /* no call slot left for a launch captured into a graph */
 
 /* ---- per-inspiral status codes (status[i]) --------------------------- */
 #define PN_ST_OK                    0  /* reached omega_f (or t_end) */
@@ -184,10 +192,11 @@ int pn_autotune(int64_t n, int64_t ld, const double* m, const double* S0, const 
 
 /*
  * pn_shutdown -- frees the library's context on the current device (its
- * call slots); the next call on that device creates it again.  Call it only
- * when no work of the library is queued or running on the device, and not
- * concurrently with other calls for that device.  PN_OK also when there is
- * no context; PN_EHIP if freeing failed.
+ * call slots and their events); the next call on that device creates it
+ * again.  Call it only when no work of the library is queued or running on
+ * the device, and not concurrently with other calls for that device; graphs
+ * captured before it must not be replayed after it.  PN_OK also when there
+ * is no context; PN_EHIP if freeing failed.
  */
 int pn_shutdown(void);
 

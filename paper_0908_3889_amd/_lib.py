@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("PN_LIB") or os.path.join(HERE, "libpn.so")
 
 # return codes
-PN_OK, PN_EINVAL, PN_ENODEV, PN_EHIP, PN_ENOMEM = 0, -1, -2, -3, -4
+PN_OK, PN_EINVAL, PN_ENODEV, PN_EHIP, PN_ENOMEM, PN_EBUSY = 0, -1, -2, -3, -4, -5
 # per-inspiral status
 STATUS = {0: "OK", 1: "DONE_AT_START", -1: "MAX_STEPS", -2: "H_UNDERFLOW", -3: "NONFINITE",
           -4: "BAD_INPUT", -5: "OMEGADOT_NONPOSITIVE", -6: "TAPE_FULL"}

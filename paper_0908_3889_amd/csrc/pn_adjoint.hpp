@@ -15,7 +15,7 @@ struct RowBar {
 
 // VJP of f = rhs(y) at y: given fbar = dL/df (10), adds (df/dy)^T fbar to
 // ybar and (df/drow)^T fbar to rb.  The primal is recomputed here (same
-// expansion and same special functions as rhs()).
+// expansion as rhs(), with the full cube root and log).
 //
 // Omega mode: the stage derivative is g = (1, f_1/f_0, ..., f_9/f_0) with
 // dt/domega = 1/f_0.  With omega_mode set, gbar (slot 0 unused) and gtbar
@@ -24,9 +24,7 @@ struct RowBar {
 //   fbar_c = gbar_c s (c >= 1),  fbar_0 = -s^2 sbar.
 //
 // gscale multiplies gbar_in (the step size of the RK adjoint recurrence).
-template <bool FAST_LOG>
-__device__ __forceinline__ void rhs_vjp(const Row& r, const TermConsts& tc, const LogBase& lb,
-                                        const double* __restrict__ y,
+__device__ __forceinline__ void rhs_vjp(const Row& r, const TermConsts& tc, const double* __restrict__ y,
                                         const double* __restrict__ gbar_in, double gscale, double gtbar,
                                         bool omega_mode, double* __restrict__ ybar, RowBar& rb) {
     // ---------------- primal ----------------
@@ -34,14 +32,7 @@ __device__ __forceinline__ void rhs_vjp(const Row& r, const TermConsts& tc, cons
     const double M = r[R_M];
     const double v = M * w;
     const double x = cbrt_real(v);
-    double lnv;
-    if (FAST_LOG) {
-        const double uu = (w - lb.w) * lb.iw;
-        if (__builtin_fabs(uu) <= 0.125) lnv = lb.lnv + log1p_small(uu);
-        else lnv = log_pos(__builtin_fabs(v));
-    } else {
-        lnv = log_pos(__builtin_fabs(v));
-    }
+    const double lnv = log_pos(__builtin_fabs(v));
     const double x2 = x * x;
     const double L0 = y[7], L1 = y[8], L2 = y[9];
     const double a0 = y[1], a1 = y[2], a2 = y[3];

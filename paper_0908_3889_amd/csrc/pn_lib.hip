@@ -23,35 +23,14 @@
 #include "pn.h"
 #include "pn_adjoint.hpp"
 #include "pn_device.hpp"
+#include "pn_slots.hpp"
+
+namespace pn {
 
 // Occupancy targets (waves per SIMD) the integration kernels are compiled
 // for; chosen by measurement (register budget 512/target per lane).
-#ifndef PN_WPE_F64
-#define PN_WPE_F64 2
-#endif
-#ifndef PN_WPE_F32
-#define PN_WPE_F32 3
-#endif
-// Where the backward pass parks the stage points Y_2..Y_6 (1: LDS, 0: a
-// global scratch row per lane) and the stage adjoints mu_2..mu_6 (1: LDS,
-// 0: registers); chosen by measurement.
-#ifndef PN_ADJ_Y_LDS
-#define PN_ADJ_Y_LDS 1
-#endif
-#ifndef PN_ADJ_MU_LDS
-#define PN_ADJ_MU_LDS 0
-#endif
-// 1: the backward pass evaluates stage logs and cube roots from the per-step
-// base as the forward does; 0: with the full functions (fewer live registers)
-#ifndef PN_ADJ_BASE
-#define PN_ADJ_BASE 0
-#endif
-// the same choice for the replay of a segment (fewer values are live there)
-#ifndef PN_ADJ_REPLAY_BASE
-#define PN_ADJ_REPLAY_BASE 0
-#endif
-
-namespace pn {
+constexpr int kWpeF64 = 2;
+constexpr int kWpeF32 = 3;
 
 // ---------------------------------------------------------------------------
 // Dormand-Prince RK5(4)7M tableau (Dormand & Prince 1980)
@@ -689,62 +668,62 @@ __device__ __forceinline__ void static_loop(const Io& io, const Uni& u, int64_t 
 }
 
 template <int BLOCK, bool RECORD>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(PN_WPE_F64)))
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(kWpeF64)))
 void integrate_persistent_f64(Uni u, unsigned long long* slot) {
     persistent_loop<F64<RECORD, false, false>>(u, slot);      // adaptive, to omega_f
 }
 
 template <int BLOCK, bool RECORD>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(PN_WPE_F64)))
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(kWpeF64)))
 void integrate_persistent_f64_modes(Uni u, unsigned long long* slot) {
     persistent_loop<F64<RECORD, false, true>>(u, slot);       // also fixed step and t_end
 }
 
 template <int BLOCK>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(PN_WPE_F32)))
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(kWpeF32)))
 void integrate_persistent_f32s(Uni u, unsigned long long* slot) {
     persistent_loop<F32Split<false, false>>(u, slot);
 }
 
 template <int BLOCK>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(PN_WPE_F32)))
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(kWpeF32)))
 void integrate_persistent_f32s_modes(Uni u, unsigned long long* slot) {
     persistent_loop<F32Split<false, true>>(u, slot);
 }
 
 // the same loops with the orbital phase integrated alongside
 template <int BLOCK>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(PN_WPE_F64)))
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(kWpeF64)))
 void integrate_persistent_f64_phase(Uni u, unsigned long long* slot) {
     persistent_loop<F64<false, true>>(u, slot);
 }
 
 template <int BLOCK>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(PN_WPE_F32)))
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(kWpeF32)))
 void integrate_persistent_f32s_phase(Uni u, unsigned long long* slot) {
     persistent_loop<F32Split<true>>(u, slot);
 }
 
 template <int BLOCK, bool RECORD>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(PN_WPE_F64)))
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(kWpeF64)))
 void integrate_static_f64(Io io, Uni u) {
     static_loop<F64<RECORD>>(io, u, (int64_t)blockIdx.x * BLOCK + threadIdx.x);
 }
 
 template <int BLOCK>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(PN_WPE_F32)))
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(kWpeF32)))
 void integrate_static_f32s(Io io, Uni u) {
     static_loop<F32Split<>>(io, u, (int64_t)blockIdx.x * BLOCK + threadIdx.x);
 }
 
 template <int BLOCK>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(PN_WPE_F64)))
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(kWpeF64)))
 void integrate_static_f64_phase(Io io, Uni u) {
     static_loop<F64<false, true>>(io, u, (int64_t)blockIdx.x * BLOCK + threadIdx.x);
 }
 
 template <int BLOCK>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(PN_WPE_F32)))
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(kWpeF32)))
 void integrate_static_f32s_phase(Io io, Uni u) {
     static_loop<F32Split<true>>(io, u, (int64_t)blockIdx.x * BLOCK + threadIdx.x);
 }
@@ -783,15 +762,14 @@ struct AdjIo {
     double* __restrict__ g_L0;          // [3][ld]
     double* __restrict__ g_w0;          // [ld]
     double* __restrict__ ws;            // [K][11][n]: per grid lane, the segment's states and steps
-    double* __restrict__ ystage;        // [60][n] (stage points outside LDS only)
     const int32_t* __restrict__ order;  // [n] or null
 };
 
 // the stage derivative: f (time mode) or g (omega mode)
-template <bool FAST = (PN_ADJ_BASE != 0)>
-__device__ __forceinline__ void stage_deriv(const Row& R, const TermConsts& tc, const LogBase& lb, const double* Y,
-                                            double* k, bool om) {
-    rhs<Row, FAST>(R, tc, lb, Y, k);
+__device__ __forceinline__ void stage_deriv(const Row& R, const TermConsts& tc, const double* Y, double* k,
+                                            bool om) {
+    const LogBase lb{};
+    rhs<Row, false>(R, tc, lb, Y, k);
     if (om) {
         const double s = 1.0 / k[0];
 #pragma unroll
@@ -802,35 +780,33 @@ __device__ __forceinline__ void stage_deriv(const Row& R, const TermConsts& tc, 
 
 // one replayed step (no error control): y <- y + h sum b_i k_i
 __device__ __forceinline__ void replay_step(const Row& R, const TermConsts& tc, double* y, double h, bool om) {
-    LogBase lb{};
-    if (PN_ADJ_REPLAY_BASE) lb = log_base(R, y);
     double k1[10], k2[10], k3[10], k4[10], k5[10], k6[10], Y[10];
-    stage_deriv<PN_ADJ_REPLAY_BASE != 0>(R, tc, lb, y, k1, om);
+    stage_deriv(R, tc, y, k1, om);
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int c = 0; c < 10; ++c) Y[c] = __builtin_fma(h * A21, k1[c], y[c]);
-    stage_deriv<PN_ADJ_REPLAY_BASE != 0>(R, tc, lb, Y, k2, om);
+    stage_deriv(R, tc, Y, k2, om);
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int c = 0; c < 10; ++c) Y[c] = __builtin_fma(h * A32, k2[c], __builtin_fma(h * A31, k1[c], y[c]));
-    stage_deriv<PN_ADJ_REPLAY_BASE != 0>(R, tc, lb, Y, k3, om);
+    stage_deriv(R, tc, Y, k3, om);
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int c = 0; c < 10; ++c)
         Y[c] = __builtin_fma(h * A43, k3[c], __builtin_fma(h * A42, k2[c], __builtin_fma(h * A41, k1[c], y[c])));
-    stage_deriv<PN_ADJ_REPLAY_BASE != 0>(R, tc, lb, Y, k4, om);
+    stage_deriv(R, tc, Y, k4, om);
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int c = 0; c < 10; ++c)
         Y[c] = __builtin_fma(h * A54, k4[c], __builtin_fma(h * A53, k3[c],
                __builtin_fma(h * A52, k2[c], __builtin_fma(h * A51, k1[c], y[c]))));
-    stage_deriv<PN_ADJ_REPLAY_BASE != 0>(R, tc, lb, Y, k5, om);
+    stage_deriv(R, tc, Y, k5, om);
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int c = 0; c < 10; ++c)
         Y[c] = __builtin_fma(h * A65, k5[c], __builtin_fma(h * A64, k4[c], __builtin_fma(h * A63, k3[c],
                __builtin_fma(h * A62, k2[c], __builtin_fma(h * A61, k1[c], y[c])))));
-    stage_deriv<PN_ADJ_REPLAY_BASE != 0>(R, tc, lb, Y, k6, om);
+    stage_deriv(R, tc, Y, k6, om);
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int c = 0; c < 10; ++c)
@@ -843,25 +819,19 @@ __device__ __forceinline__ void replay_step(const Row& R, const TermConsts& tc, 
 // whose size D = omega_f - omega depends on the state: it adds -dL/dD to
 // lam[0].
 //   ys: the state before the step (slot 0, filled by the caller) and the
-//       stage points Y_2..Y_6 (slots 1..5) of this lane; entry (s, c) at
-//       ys[(s * 10 + c) * ystride] (a global scratch row per grid lane,
-//       coalesced across the wave);
-//   ms: the stage adjoints mu_2..mu_6 of this lane in LDS; entry (j, c) at
-//       ms[(j * 10 + c) * 64], j = 0..4 for mu_2..mu_6.
+//       stage points Y_2..Y_6 (slots 1..5) of this lane in LDS; entry (s, c)
+//       at ys[(s * 10 + c) * 64];
+//   pf: the state and step size of the step reversed next (workspace column,
+//       entry c at pf[c * pfstride]), parked in nx (LDS, entry c at nx[c * 64]);
+//   the stage adjoints mu_2..mu_6 stay in registers.
 __device__ __forceinline__ void reverse_step(const Row& R, const TermConsts& tc, double h, bool om, bool last,
                                              double* lam, double lt, RowBar& rb, double* __restrict__ ys,
-                                             int64_t ystride, double* __restrict__ ms,
                                              const double* __restrict__ pf, int64_t pfstride,
                                              double* __restrict__ nx) {
-#define YS(S, C) ys[((S) * 10 + (C)) * ystride]
-#if PN_ADJ_MU_LDS
-#define MS(J, C) ms[((J) * 10 + (C)) * 64]
-#else
+#define YS(S, C) ys[((S) * 10 + (C)) * 64]
     double mreg[5][10];
 #define MS(J, C) mreg[J][C]
-    (void)ms;
-#endif
-    LogBase lb{};
+    const LogBase lb{};
     {
         double y[10];
 #pragma unroll
@@ -872,27 +842,26 @@ __device__ __forceinline__ void reverse_step(const Row& R, const TermConsts& tc,
         double nxt[11];
 #pragma unroll
         for (int c = 0; c < 11; ++c) nxt[c] = pf[c * pfstride];
-        if (PN_ADJ_BASE) lb = log_base(R, y);
         double k1[10], k2[10], k3[10], k4[10], k5[10], Y[10];
-        stage_deriv(R, tc, lb, y, k1, om);
+        stage_deriv(R, tc, y, k1, om);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int c = 0; c < 10; ++c) { Y[c] = __builtin_fma(h * A21, k1[c], y[c]); YS(1, c) = Y[c]; }
-        stage_deriv(R, tc, lb, Y, k2, om);
+        stage_deriv(R, tc, Y, k2, om);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int c = 0; c < 10; ++c) {
             Y[c] = __builtin_fma(h * A32, k2[c], __builtin_fma(h * A31, k1[c], y[c]));
             YS(2, c) = Y[c];
         }
-        stage_deriv(R, tc, lb, Y, k3, om);
+        stage_deriv(R, tc, Y, k3, om);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int c = 0; c < 10; ++c) {
             Y[c] = __builtin_fma(h * A43, k3[c], __builtin_fma(h * A42, k2[c], __builtin_fma(h * A41, k1[c], y[c])));
             YS(3, c) = Y[c];
         }
-        stage_deriv(R, tc, lb, Y, k4, om);
+        stage_deriv(R, tc, Y, k4, om);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int c = 0; c < 10; ++c) {
@@ -900,7 +869,7 @@ __device__ __forceinline__ void reverse_step(const Row& R, const TermConsts& tc,
                    __builtin_fma(h * A52, k2[c], __builtin_fma(h * A51, k1[c], y[c]))));
             YS(4, c) = Y[c];
         }
-        stage_deriv(R, tc, lb, Y, k5, om);
+        stage_deriv(R, tc, Y, k5, om);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int c = 0; c < 10; ++c)
@@ -927,10 +896,10 @@ __device__ __forceinline__ void reverse_step(const Row& R, const TermConsts& tc,
             Lh[c] = (LAMEXPR);                                                                   \
             mu[c] = 0.0;                                                                         \
         }                                                                                        \
-        rhs_vjp<PN_ADJ_BASE>(R, tc, lb, Yi, Lh, h, lt * h * (BI), om, mu, rb);                   \
+        rhs_vjp(R, tc, Yi, Lh, h, lt * h * (BI), om, mu, rb);                                       \
         if (last) {                                                                              \
             double f[10];                                                                        \
-            rhs<Row, PN_ADJ_BASE>(R, tc, lb, Yi, f);                                             \
+            rhs<Row, false>(R, tc, lb, Yi, f);                                                   \
             const double s = 1.0 / f[0];                                                         \
             double dot = Lh[0];                                                                  \
             _Pragma("unroll") for (int c = 1; c < 10; ++c) dot = __builtin_fma(f[c] * s, Lh[c], dot); \
@@ -964,8 +933,7 @@ __device__ __forceinline__ void reverse_step(const Row& R, const TermConsts& tc,
 // wsl: this grid lane's column of the segment workspace, entry (k, c) at
 // wsl[(k * 11 + c) * n] (c < 10: the state before step k of the segment,
 // c = 10: that step's size), so that a wave's accesses are coalesced.
-__device__ void adjoint_one(const AdjIo& io, const AdjUni& u, int64_t idx, double* wsl, double* ys,
-                            int64_t ystride, double* ms, double* nx) {
+__device__ void adjoint_one(const AdjIo& io, const AdjUni& u, int64_t idx, double* wsl, double* ys, double* nx) {
     const int64_t ld = u.ld;
     const int st = io.status[idx];
     const double* tp = u.tape + idx * u.tape_stride;
@@ -1042,13 +1010,13 @@ __device__ void adjoint_one(const AdjIo& io, const AdjUni& u, int64_t idx, doubl
         }
         for (int k = k1 - 1; k >= k0; --k) {
 #pragma unroll
-            for (int c = 0; c < 10; ++c) ys[c * ystride] = nx[c * 64];
+            for (int c = 0; c < 10; ++c) ys[c * 64] = nx[c * 64];
             const double h = nx[10 * 64];
             const bool om = k >= nt;
             const bool last = om && k == N - 1;
             // the step reversed next (k - 1; at k0 a valid row, not used)
             const double* pf = &WS((k > k0 ? k - 1 : k0) - k0, 0);
-            reverse_step(R, u.tc, h, om, last, lam, lt, rb, ys, ystride, ms, pf, wstride, nx);
+            reverse_step(R, u.tc, h, om, last, lam, lt, rb, ys, pf, wstride, nx);
         }
     }
 #undef WS
@@ -1074,29 +1042,15 @@ __device__ void adjoint_one(const AdjIo& io, const AdjUni& u, int64_t idx, doubl
 
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void adjoint_kernel(AdjIo io, AdjUni u) {
-#if PN_ADJ_MU_LDS
-    __shared__ double s_mu[BLOCK / 64][50][64];     // stage adjoints mu_2..mu_6 of each lane
-    double* ms = &s_mu[threadIdx.x / 64][0][lane_id()];
-#else
-    double* ms = nullptr;
-#endif
-#if PN_ADJ_Y_LDS
     __shared__ double s_ys[BLOCK / 64][60][64];     // y and the stage points of each lane
     double* ys = &s_ys[threadIdx.x / 64][0][lane_id()];
-    const int64_t ystride = 64;
-#endif
     __shared__ double s_nx[BLOCK / 64][11][64];     // state and step size of the step reversed next
     double* nx = &s_nx[threadIdx.x / 64][0][lane_id()];
     const int64_t j = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
     if (j >= u.n) return;
     const int64_t idx = io.order ? (int64_t)io.order[j] : j;
     if (idx < 0 || idx >= u.n) return;      // not a permutation entry: nothing to do
-#if !PN_ADJ_Y_LDS
-    // the stage-point scratch row of grid lane j: entry e at ystage[e * n + j]
-    double* ys = io.ystage + j;
-    const int64_t ystride = u.n;
-#endif
-    adjoint_one(io, u, idx, io.ws + j, ys, ystride, ms, nx);
+    adjoint_one(io, u, idx, io.ws + j, ys, nx);
 }
 
 // Zeroes the work counter of a persistent launch and writes its launch
@@ -1144,13 +1098,31 @@ __global__ void observables_kernel(int64_t n, int64_t ld, const double* __restri
 // Host side: per-device context, argument checks, launches
 // ---------------------------------------------------------------------------
 
-constexpr int kCounterSlots = 1024;
+// The HIP side of the call-slot bookkeeping (pn_slots.hpp).
+struct HipSlotOps {
+    using Stream = hipStream_t;
+    using Event = hipEvent_t;
+    int capturing(Stream s, bool* cap) {
+        hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(s, &st) != hipSuccess) return PN_EHIP;
+        *cap = st != hipStreamCaptureStatusNone;
+        return 0;
+    }
+    int create(Event* e) { return hipEventCreateWithFlags(e, hipEventDisableTiming) == hipSuccess ? 0 : PN_EHIP; }
+    int wait(Stream s, Event e) { return hipStreamWaitEvent(s, e, 0) == hipSuccess ? 0 : PN_EHIP; }
+    int record(Event e, Stream s) { return hipEventRecord(e, s) == hipSuccess ? 0 : PN_EHIP; }
+    int destroy(Event e) { return hipEventDestroy(e) == hipSuccess ? 0 : PN_EHIP; }
+};
+
+// call slots: 1024 taken in turn by direct calls, 4096 for captured calls
+using Slots = SlotTable<HipSlotOps, 1024, 4096>;
+constexpr int kCounterSlots = Slots::kRing + Slots::kCapture;
 
 struct DevCtx {
     std::atomic<bool> ready{false};
     int cus = 0;
     unsigned long long* counters = nullptr;   // kCounterSlots slots: work counter, launch descriptor
-    std::atomic<unsigned> next{0};
+    Slots slots;
 };
 
 constexpr int kMaxDevices = 64;
@@ -1186,9 +1158,11 @@ int release_ctx() {
     DevCtx& c = g_ctx[dev];
     if (!c.ready.load(std::memory_order_relaxed)) return PN_OK;
     c.ready.store(false, std::memory_order_release);
+    HipSlotOps ops;
+    const int re = c.slots.reset(ops);
     const hipError_t e = hipFree(c.counters);
     c.counters = nullptr;
-    return e == hipSuccess ? PN_OK : PN_EHIP;
+    return (e == hipSuccess && re == 0) ? PN_OK : PN_EHIP;
 }
 
 TermConsts term_consts(int terms) {
@@ -1200,19 +1174,25 @@ TermConsts term_consts(int terms) {
 }
 
 template <int BLOCK>
-hipError_t launch_forward(const Io& io, const Uni& u, int precision, int schedule, int waves_per_simd, int cus,
-                          unsigned long long* counter, hipStream_t s) {
+hipError_t launch_static(const Io& io, const Uni& u, int precision, hipStream_t s) {
     const bool f32 = precision == PN_PREC_FP32_SPLIT;
     const bool ph = io.phase != nullptr;
-    if (schedule == PN_SCHED_STATIC) {
-        const int64_t grid = (u.n + BLOCK - 1) / BLOCK;
-        if (ph && f32) hipLaunchKernelGGL(integrate_static_f32s_phase<BLOCK>, dim3((unsigned)grid), dim3(BLOCK), 0, s, io, u);
-        else if (ph) hipLaunchKernelGGL(integrate_static_f64_phase<BLOCK>, dim3((unsigned)grid), dim3(BLOCK), 0, s, io, u);
-        else if (f32) hipLaunchKernelGGL(integrate_static_f32s<BLOCK>, dim3((unsigned)grid), dim3(BLOCK), 0, s, io, u);
-        else if (u.tape) hipLaunchKernelGGL((integrate_static_f64<BLOCK, true>), dim3((unsigned)grid), dim3(BLOCK), 0, s, io, u);
-        else hipLaunchKernelGGL((integrate_static_f64<BLOCK, false>), dim3((unsigned)grid), dim3(BLOCK), 0, s, io, u);
-        return hipGetLastError();
-    }
+    const int64_t grid = (u.n + BLOCK - 1) / BLOCK;
+    if (ph && f32) hipLaunchKernelGGL(integrate_static_f32s_phase<BLOCK>, dim3((unsigned)grid), dim3(BLOCK), 0, s, io, u);
+    else if (ph) hipLaunchKernelGGL(integrate_static_f64_phase<BLOCK>, dim3((unsigned)grid), dim3(BLOCK), 0, s, io, u);
+    else if (f32) hipLaunchKernelGGL(integrate_static_f32s<BLOCK>, dim3((unsigned)grid), dim3(BLOCK), 0, s, io, u);
+    else if (u.tape) hipLaunchKernelGGL((integrate_static_f64<BLOCK, true>), dim3((unsigned)grid), dim3(BLOCK), 0, s, io, u);
+    else hipLaunchKernelGGL((integrate_static_f64<BLOCK, false>), dim3((unsigned)grid), dim3(BLOCK), 0, s, io, u);
+    return hipGetLastError();
+}
+
+// The persistent launch on the call slot `counter`: prepare_launch zeroes the
+// slot's work counter and writes the descriptor, then the persistent grid.
+template <int BLOCK>
+hipError_t launch_persistent(const Io& io, const Uni& u, int precision, int waves_per_simd, int cus,
+                             unsigned long long* counter, hipStream_t s) {
+    const bool f32 = precision == PN_PREC_FP32_SPLIT;
+    const bool ph = io.phase != nullptr;
     LaunchDesc desc;
     desc.io = io;
     desc.u = u;
@@ -1262,6 +1242,7 @@ const char* pn_strerror(int code) {
         case PN_ENODEV: return "PN_ENODEV: no usable gfx950 device is current";
         case PN_EHIP: return "PN_EHIP: a HIP runtime call or kernel launch failed";
         case PN_ENOMEM: return "PN_ENOMEM: device context allocation failed";
+        case PN_EBUSY: return "PN_EBUSY: every call slot for launches captured into graphs is taken (pn_shutdown frees them)";
         default: return "unknown pn error code";
     }
 }
@@ -1292,7 +1273,7 @@ static int integrate_impl(int64_t n, int64_t ld, const double* m, const double* 
     const int block = o.block ? o.block : 256;
     if (block != 64 && block != 128 && block != 256 && block != 512) return PN_EINVAL;
     const int wps = o.waves_per_simd ? o.waves_per_simd
-                                     : (o.precision == PN_PREC_FP32_SPLIT ? PN_WPE_F32 : PN_WPE_F64);
+                                     : (o.precision == PN_PREC_FP32_SPLIT ? kWpeF32 : kWpeF64);
     if (wps < 1 || wps > 8) return PN_EINVAL;
     const int refill = o.refill_min ? o.refill_min : 4;
     if (refill < 1 || refill > 64) return PN_EINVAL;
@@ -1336,16 +1317,29 @@ static int integrate_impl(int64_t n, int64_t ld, const double* m, const double* 
     io.y = y_final; io.t = t_final; io.steps = steps; io.status = status; io.dots = dots;
     io.phase = phase;
 
-    unsigned long long* counter = ctx->counters + (size_t)(ctx->next.fetch_add(1) % kCounterSlots) * kSlotWords;
     hipStream_t s = (hipStream_t)stream;
-    hipError_t e;
-    switch (block) {
-        case 64: e = launch_forward<64>(io, u, o.precision, o.schedule, wps, ctx->cus, counter, s); break;
-        case 128: e = launch_forward<128>(io, u, o.precision, o.schedule, wps, ctx->cus, counter, s); break;
-        case 512: e = launch_forward<512>(io, u, o.precision, o.schedule, wps, ctx->cus, counter, s); break;
-        default: e = launch_forward<256>(io, u, o.precision, o.schedule, wps, ctx->cus, counter, s); break;
+    if (o.schedule == PN_SCHED_STATIC) {
+        hipError_t e;
+        switch (block) {
+            case 64: e = launch_static<64>(io, u, o.precision, s); break;
+            case 128: e = launch_static<128>(io, u, o.precision, s); break;
+            case 512: e = launch_static<512>(io, u, o.precision, s); break;
+            default: e = launch_static<256>(io, u, o.precision, s); break;
+        }
+        return e == hipSuccess ? PN_OK : PN_EHIP;
     }
-    return e == hipSuccess ? PN_OK : PN_EHIP;
+    HipSlotOps ops;
+    return ctx->slots.run(ops, s, PN_EBUSY, [&](int k) {
+        unsigned long long* counter = ctx->counters + (size_t)k * kSlotWords;
+        hipError_t e;
+        switch (block) {
+            case 64: e = launch_persistent<64>(io, u, o.precision, wps, ctx->cus, counter, s); break;
+            case 128: e = launch_persistent<128>(io, u, o.precision, wps, ctx->cus, counter, s); break;
+            case 512: e = launch_persistent<512>(io, u, o.precision, wps, ctx->cus, counter, s); break;
+            default: e = launch_persistent<256>(io, u, o.precision, wps, ctx->cus, counter, s); break;
+        }
+        return e == hipSuccess ? PN_OK : PN_EHIP;
+    });
 }
 
 int pn_integrate(int64_t n, int64_t ld, const double* m, const double* S0, const double* L0,
@@ -1429,9 +1423,8 @@ int pn_integrate_record(int64_t n, int64_t ld, const double* m, const double* S0
 
 size_t pn_adjoint_workspace_bytes(int64_t n, int32_t ckpt_every) {
     if (n < 0 || n > PN_MAX_N || ckpt_every < 1) return 0;
-    // the replayed states of one segment per inspiral, plus the stage points
-    // when those are not kept in LDS
-    return (size_t)n * ((size_t)ckpt_every * 11 + (PN_ADJ_Y_LDS ? 0 : 60)) * sizeof(double);
+    // the replayed states and step sizes of one segment per inspiral
+    return (size_t)n * (size_t)ckpt_every * 11 * sizeof(double);
 }
 
 int pn_integrate_adjoint(int64_t n, int64_t ld, const double* m, double omega_f, const pn_opts* opt,
@@ -1468,7 +1461,6 @@ int pn_integrate_adjoint(int64_t n, int64_t ld, const double* m, double omega_f,
     io.m = m; io.status = status; io.gy = gy_final; io.gt = gt_final;
     io.g_m = g_m; io.g_S0 = g_S0; io.g_L0 = g_L0; io.g_w0 = g_omega0; io.order = order;
     io.ws = workspace;                                       // [K][11][n] replayed states and steps
-    io.ystage = PN_ADJ_Y_LDS ? nullptr : workspace + n * (int64_t)ckpt_every * 11;   // [60][n] stage points
     const int64_t grid = (n + 127) / 128;
     hipLaunchKernelGGL(adjoint_kernel<128>, dim3((unsigned)grid), dim3(128), 0, (hipStream_t)stream, io, u);
     return hipGetLastError() == hipSuccess ? PN_OK : PN_EHIP;

@@ -37,7 +37,7 @@ def test_binding_covers_the_header():
 
 
 def test_strerror_and_version(lib):
-    for code in (0, -1, -2, -3, -4):
+    for code in (0, -1, -2, -3, -4, -5):
         assert lib.pn_strerror(code).decode().startswith("PN_")
     assert lib.pn_version().decode()
 

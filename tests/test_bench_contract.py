@@ -85,6 +85,35 @@ def test_bench_line_on_the_gpu():
 
 
 @pytest.mark.gpu
+def test_bench_legs_on_the_gpu():
+    """The adjoint, FP32-split and batching legs of the default line, on small
+    prefixes of their workloads."""
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_0908_3889_amd import api
+    stream = torch.cuda.current_stream()
+    adj = bench.leg_adjoint(api, P, stream, ks=(16, 64), reps=2, n=2048)
+    assert adj["n"] == 2048 and set(adj["per_K"]) == {"16", "64"}
+    for v in adj["per_K"].values():
+        assert v["ok"] == 2048 and v["grad_finite"] and v["r_bwd"] > 0 and v["r_ckpt"] > 0
+        assert abs(v["r_bwd"] - v["adjoint_ms"] / adj["fwd_ms"]) < 1e-12
+    pop = P.generate("q1to4_1M", 8192)
+    d = api.to_device(pop)
+    out = api.pn_integrate(d["m"], d["S"], d["L"], d["omega0"], pop["omega_f"], pop["tol"], stream=stream)
+    ref64 = {k: v.cpu().numpy() for k, v in out.items() if v is not None}
+    f32 = bench.leg_fp32split(api, pop, d, ref64, stream, reps=2)
+    assert f32["status_ok"] == 8192 and 0 < f32["frac"] < 1
+    e = f32["error_vs_fp64"]
+    assert set(e) == {"S1h.S2h", "S1h.Lh", "S2h.Lh", "S1 (|dS1|/|S1(0)|)", "S2 (|dS2|/|S2(0)|)", "L_hat (|dL|)",
+                      "t (relative)", "phase (relative)"}
+    assert all(0 <= v["p99"] <= v["max"] < 1e-2 for v in e.values())
+    bat = bench.leg_batching(api, P, stream, reps=1, n=16384)
+    assert bat["persistent"]["status_ok"] == 16384 and bat["static"]["status_ok"] == 16384
+    assert bat["static_over_persistent"] > 0
+
+
+@pytest.mark.gpu
 def test_bench_cpu_baseline_and_crosscheck_on_the_gpu():
     torch = pytest.importorskip("torch")
     if not torch.cuda.is_available():

@@ -68,6 +68,10 @@ def test_fixed_step_phase_parity(workload, h):
     np.testing.assert_array_equal(rg["steps"][:2], ro["steps"][:2])
     bound = np.maximum(1e-12, 1e-15 * ro["steps"][0])
     rel = np.abs(rg["phase"] / ro["phase"] - 1)
+    steps = ro["steps"][0]
+    print(f"\nfixed-step phase {workload} h={h}: max rel {rel.max():.3e}, median {np.median(rel):.3e}, "
+          f"max rel/step {(rel / steps).max():.3e}, max rel/sqrt(step) {(rel / np.sqrt(steps)).max():.3e}, "
+          f"steps {steps.min()}..{steps.max()}", flush=True)
     assert (rel < bound).all(), (rel / bound).max()
 
 
@@ -116,7 +120,7 @@ def test_phase_of_special_statuses_and_sizes():
     assert rg["status"][3] == 1 and rg["status"][5] == -4
     assert rg["phase"][3] == 0.0 and rg["phase"][5] == 0.0
     ok = ro["status"] == 0
-    assert np.abs(rg["phase"] / ro["phase"] - 1)[ok].max() < 1e-9
+    assert np.abs(rg["phase"][ok] / ro["phase"][ok] - 1).max() < 1e-9
     # n = 0 launches nothing; n = 1 is one lane of one wave
     d = api.to_device(P.generate("adjoint_64k", 1))
     out = api.pn_integrate_phase(d["m"], d["S"], d["L"], d["omega0"], 0.05, 1e-8)
