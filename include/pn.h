@@ -152,6 +152,31 @@ int pn_integrate(int64_t n, int64_t ld,
                  double* dots, void* stream);
 
 /*
+ * pn_integrate_noalloc -- pn_integrate for callers that cannot allocate
+ * device memory: code being captured into a HIP graph, tight serving loops,
+ * harnesses that forbid hipMalloc.  Same arguments, kernels, outputs and
+ * errors as pn_integrate, bit for bit; the caller still owns every input and
+ * output.  The call allocates nothing: no hipMalloc or hipFree, no event, no
+ * library context.  The only device memory besides the caller's buffers is a
+ * fixed 512-byte scratch array in the library (the persistent launch's work
+ * counter and launch descriptor), one copy per device, held until the
+ * process ends; its size does not depend on n, so every n that pn_integrate
+ * accepts (0 <= n <= ld <= PN_MAX_N) fits, and larger n is PN_EINVAL.  The
+ * counter is cleared by a kernel on `stream` at the start of each call.
+ * Every pn_integrate_noalloc call on a device shares that array: calls on one
+ * stream are ordered and safe, but calls that overlap on one device (several
+ * streams or threads without ordering between them, or a captured graph
+ * replayed while another such call runs) race and give wrong outputs.  The
+ * first call on a device looks up the array's device address
+ * (hipGetSymbolAddress); PN_EHIP if that fails.
+ */
+int pn_integrate_noalloc(int64_t n, int64_t ld,
+                         const double* m, const double* S0, const double* L0, const double* omega0,
+                         double omega_f, double tol, const pn_opts* opt,
+                         double* y_final, double* t_final, int32_t* steps, int32_t* status,
+                         double* dots, void* stream);
+
+/*
  * pn_integrate_phase -- pn_integrate that also integrates the orbital phase
  * Phi(t) = integral of omega dt from Phi(0) = 0 (a quantity the paper does not
  * use; the phase of waveform-style outputs).  Each accepted step adds h times

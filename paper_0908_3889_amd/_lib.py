@@ -28,7 +28,7 @@ EXPORTS = ("pn_integrate", "pn_rhs", "pn_observables", "pn_strerror", "pn_versio
            "pn_tape_stride", "pn_integrate_record", "pn_adjoint_workspace_bytes",
            "pn_integrate_adjoint", "pn_histogram", "pn_histogram2d", "pn_pearson", "pn_kde",
            "pn_ks_workspace_bytes", "pn_ks_uniform", "pn_stats_workspace_bytes", "pn_generate",
-           "pn_autotune", "pn_integrate_phase", "pn_fma_rate", "pn_shutdown")
+           "pn_autotune", "pn_integrate_phase", "pn_fma_rate", "pn_shutdown", "pn_integrate_noalloc")
 
 
 class PnOpts(C.Structure):
@@ -73,6 +73,8 @@ def load():
     popts = C.POINTER(PnOpts)
     L.pn_integrate.argtypes = [i64, i64, vp, vp, vp, vp, dbl, dbl, popts, vp, vp, vp, vp, vp, vp]
     L.pn_integrate.restype = C.c_int
+    L.pn_integrate_noalloc.argtypes = [i64, i64, vp, vp, vp, vp, dbl, dbl, popts, vp, vp, vp, vp, vp, vp]
+    L.pn_integrate_noalloc.restype = C.c_int
     L.pn_integrate_phase.argtypes = [i64, i64, vp, vp, vp, vp, dbl, dbl, popts, vp, vp, vp, vp, vp, vp, vp]
     L.pn_integrate_phase.restype = C.c_int
     L.pn_fma_rate.argtypes = [C.c_int32, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double), vp]

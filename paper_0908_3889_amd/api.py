@@ -81,7 +81,18 @@ def pn_integrate(m, S0, L0, omega0, omega_f, tol, opts: PnOpts | None = None, ou
     Returns dict(y [10, n], t [n], steps [3, n] int32, status [n] int32,
     dots [3, n] or None).  Asynchronous on the current stream.
     """
-    return _integrate(False, m, S0, L0, omega0, omega_f, tol, opts, out, dots, stream)
+    return _integrate("plain", m, S0, L0, omega0, omega_f, tol, opts, out, dots, stream)
+
+
+def pn_integrate_noalloc(m, S0, L0, omega0, omega_f, tol, out: dict, opts: PnOpts | None = None,
+                         stream=None) -> dict:
+    """pn_integrate through the entry point that allocates no device memory
+    (for graph capture and serving loops): `out` must be preallocated
+    (alloc_outputs); the library uses a fixed scratch array of its own.
+    Calls that overlap on one device race; calls on one stream are safe."""
+    if out is None:
+        raise ValueError("pn_integrate_noalloc needs preallocated outputs (alloc_outputs)")
+    return _integrate("noalloc", m, S0, L0, omega0, omega_f, tol, opts, out, out.get("dots") is not None, stream)
 
 
 def pn_integrate_phase(m, S0, L0, omega0, omega_f, tol, opts: PnOpts | None = None, out=None,
@@ -89,10 +100,10 @@ def pn_integrate_phase(m, S0, L0, omega0, omega_f, tol, opts: PnOpts | None = No
     """pn_integrate plus the orbital phase Phi = integral of omega dt at
     t_final: out["phase"] [n] float64.  Every other output is bit-identical
     to pn_integrate's."""
-    return _integrate(True, m, S0, L0, omega0, omega_f, tol, opts, out, dots, stream)
+    return _integrate("phase", m, S0, L0, omega0, omega_f, tol, opts, out, dots, stream)
 
 
-def _integrate(phase, m, S0, L0, omega0, omega_f, tol, opts, out, dots, stream) -> dict:
+def _integrate(kind, m, S0, L0, omega0, omega_f, tol, opts, out, dots, stream) -> dict:
     n = int(omega0.shape[0])
     _soa(omega0, 1, n, "omega0")
     _soa(m, 2, n, "m"); _soa(S0, 6, n, "S0"); _soa(L0, 3, n, "L0")
@@ -106,7 +117,7 @@ def _integrate(phase, m, S0, L0, omega0, omega_f, tol, opts, out, dots, stream) 
     if out.get("dots") is not None:
         _soa(out["dots"], 3, n, "dots")
         lds.add(_ld(out["dots"], n))
-    if phase:
+    if kind == "phase":
         if out.get("phase") is None:
             out["phase"] = torch.empty((n,), dtype=torch.float64, device=omega0.device)
         _soa(out["phase"], 1, n, "phase")
@@ -117,7 +128,10 @@ def _integrate(phase, m, S0, L0, omega0, omega_f, tol, opts, out, dots, stream) 
     p = lambda t: C.c_void_p(t.data_ptr()) if t is not None else None
     args = (n, ld, p(m), p(S0), p(L0), p(omega0), float(omega_f), float(tol), C.byref(o), p(out["y"]),
             p(out["t"]), p(out["steps"]), p(out["status"]), p(out.get("dots")))
-    if phase:
+    if kind == "noalloc":
+        rc = load().pn_integrate_noalloc(*args, _stream(stream))
+        check(rc, "pn_integrate_noalloc")
+    elif kind == "phase":
         rc = load().pn_integrate_phase(*args, p(out["phase"]), _stream(stream))
         check(rc, "pn_integrate_phase")
     else:

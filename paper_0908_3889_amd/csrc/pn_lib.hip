@@ -1151,6 +1151,45 @@ int get_ctx(DevCtx** out) {
     return PN_OK;
 }
 
+// pn_integrate_noalloc: the call slot of its persistent launches (work
+// counter and launch descriptor, 512 B) is this file-scope device array, so
+// that the call allocates nothing.  Each device holds its own copy; host code
+// uses the address hipGetSymbolAddress returns for the current device, never
+// the array's name.  Every such call on a device shares the array: calls that
+// overlap on one device race.
+constexpr int kScratchWords = kSlotWords;
+static __device__ __align__(256) unsigned long long scratch[kScratchWords];
+
+struct ScratchDev {
+    std::atomic<bool> ready{false};
+    unsigned long long* ptr = nullptr;   // device address of `scratch` on this device
+    int cus = 0;
+};
+ScratchDev g_scratch[kMaxDevices];
+
+// Once per device, with that device current: its address of `scratch` and
+// its compute-unit count (no allocation).
+int get_scratch(ScratchDev** out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return PN_ENODEV;
+    ScratchDev& d = g_scratch[dev];
+    if (!d.ready.load(std::memory_order_acquire)) {
+        std::lock_guard<std::mutex> lk(g_ctx_mu);
+        if (!d.ready.load(std::memory_order_relaxed)) {
+            hipDeviceProp_t prop;
+            if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return PN_ENODEV;
+            if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return PN_ENODEV;
+            void* p = nullptr;
+            if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || p == nullptr) return PN_EHIP;
+            d.ptr = static_cast<unsigned long long*>(p);
+            d.cus = prop.multiProcessorCount;
+            d.ready.store(true, std::memory_order_release);
+        }
+    }
+    *out = &d;
+    return PN_OK;
+}
+
 int release_ctx() {
     int dev = -1;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return PN_ENODEV;
@@ -1254,7 +1293,8 @@ int pn_shutdown(void) { return release_ctx(); }
 static int integrate_impl(int64_t n, int64_t ld, const double* m, const double* S0, const double* L0,
                           const double* omega0, double omega_f, double tol, const pn_opts* opt,
                           double* y_final, double* t_final, int32_t* steps, int32_t* status, double* dots,
-                          double* tape, int64_t cap_steps, int32_t ckpt_every, double* phase, void* stream) {
+                          double* tape, int64_t cap_steps, int32_t ckpt_every, double* phase, void* stream,
+                          bool noalloc = false) {
     pn_opts o;
     std::memset(&o, 0, sizeof(o));
     if (opt) o = *opt;
@@ -1286,7 +1326,8 @@ static int integrate_impl(int64_t n, int64_t ld, const double* m, const double* 
     if (n == 0) return PN_OK;
 
     DevCtx* ctx = nullptr;
-    int rc = get_ctx(&ctx);
+    ScratchDev* sd = nullptr;
+    const int rc = noalloc ? get_scratch(&sd) : get_ctx(&ctx);
     if (rc != PN_OK) return rc;
 
     Uni u;
@@ -1328,18 +1369,21 @@ static int integrate_impl(int64_t n, int64_t ld, const double* m, const double* 
         }
         return e == hipSuccess ? PN_OK : PN_EHIP;
     }
-    HipSlotOps ops;
-    return ctx->slots.run(ops, s, PN_EBUSY, [&](int k) {
-        unsigned long long* counter = ctx->counters + (size_t)k * kSlotWords;
+    const int cus = noalloc ? sd->cus : ctx->cus;
+    auto launch = [&](unsigned long long* counter) {
         hipError_t e;
         switch (block) {
-            case 64: e = launch_persistent<64>(io, u, o.precision, wps, ctx->cus, counter, s); break;
-            case 128: e = launch_persistent<128>(io, u, o.precision, wps, ctx->cus, counter, s); break;
-            case 512: e = launch_persistent<512>(io, u, o.precision, wps, ctx->cus, counter, s); break;
-            default: e = launch_persistent<256>(io, u, o.precision, wps, ctx->cus, counter, s); break;
+            case 64: e = launch_persistent<64>(io, u, o.precision, wps, cus, counter, s); break;
+            case 128: e = launch_persistent<128>(io, u, o.precision, wps, cus, counter, s); break;
+            case 512: e = launch_persistent<512>(io, u, o.precision, wps, cus, counter, s); break;
+            default: e = launch_persistent<256>(io, u, o.precision, wps, cus, counter, s); break;
         }
         return e == hipSuccess ? PN_OK : PN_EHIP;
-    });
+    };
+    if (noalloc) return launch(sd->ptr);
+    HipSlotOps ops;
+    return ctx->slots.run(ops, s, PN_EBUSY,
+                          [&](int k) { return launch(ctx->counters + (size_t)k * kSlotWords); });
 }
 
 int pn_integrate(int64_t n, int64_t ld, const double* m, const double* S0, const double* L0,
@@ -1348,6 +1392,14 @@ int pn_integrate(int64_t n, int64_t ld, const double* m, const double* S0, const
                  void* stream) {
     return integrate_impl(n, ld, m, S0, L0, omega0, omega_f, tol, opt, y_final, t_final, steps, status, dots,
                           nullptr, 0, 0, nullptr, stream);
+}
+
+int pn_integrate_noalloc(int64_t n, int64_t ld, const double* m, const double* S0, const double* L0,
+                         const double* omega0, double omega_f, double tol, const pn_opts* opt,
+                         double* y_final, double* t_final, int32_t* steps, int32_t* status, double* dots,
+                         void* stream) {
+    return integrate_impl(n, ld, m, S0, L0, omega0, omega_f, tol, opt, y_final, t_final, steps, status, dots,
+                          nullptr, 0, 0, nullptr, stream, true);
 }
 
 int pn_integrate_phase(int64_t n, int64_t ld, const double* m, const double* S0, const double* L0,
