@@ -23,6 +23,25 @@ __device__ __forceinline__ double fma3(double a, double b, double c) {
     return d;
 }
 
+// max(|a|, |b|) as one instruction.  The compiler's fmax first quiets each
+// operand (a signalling NaN must not pass through) at the cost of two more
+// instructions; the operands here are results of arithmetic, never
+// signalling NaNs.
+__device__ __forceinline__ double fmax_abs(double a, double b) {
+    double d;
+    asm("v_max_f64 %0, |%1|, |%2|" : "=v"(d) : "v"(a), "v"(b));
+    return d;
+}
+
+// a*b + k for a constant k, as the three-address FP64 FMA with k in a scalar
+// register pair: Horner chains with constant coefficients otherwise keep the
+// coefficients in vector registers and copy each before a two-address FMA.
+__device__ __forceinline__ double fma_k(double a, double b, double k) {
+    double d;
+    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "s"(k));
+    return d;
+}
+
 // ---------------------------------------------------------------------------
 // FP64 special functions.  Each states the range it accepts; the callers
 // guarantee or clamp it.
@@ -110,20 +129,30 @@ __device__ __forceinline__ double log_pos(double v) {
     return __builtin_fma(de, LN2_HI, __builtin_fma(de, LN2_LO, lnm));
 }
 
-// z^(-1/10) for z in [2^-30, 2^30] (callers clamp): FP32 seed, then two Newton
-// steps of y <- y (11 - z y^10) / 10, each squaring the relative error
-// (times 5.5).
-__device__ __forceinline__ double pow_m_tenth(double z) {
+// max(a, k) and min(a, k) for a constant k as one instruction each (see
+// fmax_abs: no quieting of the operands, which are never signalling NaNs).
+__device__ __forceinline__ double fmax_k(double a, double k) {
+    double d;
+    asm("v_max_f64 %0, %1, %2" : "=v"(d) : "v"(a), "s"(k));
+    return d;
+}
+__device__ __forceinline__ double fmin_k(double a, double k) {
+    double d;
+    asm("v_min_f64 %0, %1, %2" : "=v"(d) : "v"(a), "s"(k));
+    return d;
+}
+
+// c z^(-1/10) for z in [2^-30, 2^30] (callers clamp): FP32 seed (relative
+// error below 1e-7 over that range), then one Newton step of
+// y <- y (11 - z y^10) / 10, which leaves 5.5 times its square (< 1e-13).
+// The result only scales the next step size.
+__device__ __forceinline__ double pow_m_tenth_scaled(double z, double c) {
     const float zf = (float)z;
-    double y = (double)__builtin_amdgcn_exp2f(__builtin_amdgcn_logf(zf) * -0.1f);
-#pragma unroll
-    for (int it = 0; it < 2; ++it) {
-        const double y2 = y * y;
-        const double y5 = (y2 * y2) * y;
-        const double t = __builtin_fma(-z, y5 * y5, 11.0);
-        y = (y * t) * 0.1;
-    }
-    return y;
+    const double y = (double)__builtin_amdgcn_exp2f(__builtin_amdgcn_logf(zf) * -0.1f);
+    const double y2 = y * y;
+    const double y5 = (y2 * y2) * y;
+    const double t = __builtin_fma(-z, y5 * y5, 11.0);
+    return (y * t) * (0.1 * c);
 }
 
 // ---------------------------------------------------------------------------
@@ -206,42 +235,47 @@ __device__ __forceinline__ void make_row(RowT& r, double m1, double m2, int term
     r.set(R_LAM, 1.0 / (eta * M * M));
 }
 
-// ln(1+u) for |u| <= 1/8: 2 atanh(s), s = u/(2+u), |s| <= 0.0589, by the
-// series 2 (s + s^3/3 + ... + s^11/11) (relative remainder < 2e-16).
-__device__ __forceinline__ double log1p_small(double u) {
-    const double d = 2.0 + u;
-    const double rd = rcp_1step(d);     // the residual correction below restores s to rounding
-    double s = u * rd;
-    s = __builtin_fma(__builtin_fma(-s, d, u), rd, s);
-    const double s2 = s * s;
-    double p = 1.0 / 11.0;
-    p = fma3(p, s2, 1.0 / 9.0);
-    p = fma3(p, s2, 1.0 / 7.0);
-    p = fma3(p, s2, 1.0 / 5.0);
-    p = fma3(p, s2, 1.0 / 3.0);
-    const double s2x = s + s;
-    return __builtin_fma(s2x * s2, p, s2x);
+// The stage points of a step lie close to its base point: with
+// u = (w_s - w_n)/w_n, |u| <= 1/16 on all but about 2 in 10^4 steps of the
+// workloads (the rest take the full log and cube root).  There
+//   (1+u)^{1/3} - 1 = w = u (1/3 + u Q(u)),
+//   ln(1+u) = 3 ln(1+w) = w (3 + w R3(w)),
+// with Q of degree 8 on [-1/16, 1/16] and R3 of degree 5 on the matching
+// w in [-0.02130, 0.02041], each interpolated at its Chebyshev nodes in 60-digit
+// arithmetic.  Largest errors: |u^2 dQ| < 2.5e-18 (relative, in the cube
+// root) and |w^2 dR3| < 4.5e-16 (absolute, in ln|M w|, whose weight in
+// Eq. (1) is at most (1712/315) x^6 < 0.014).
+constexpr double kSmallU = 0.0625;
+
+__device__ __forceinline__ double cbrt1p_small_m1(double u) {
+    double q = -0.01177066091614973521624749;
+    q = fma_k(q, u, 0.0135791980361245423248501);
+    q = fma_k(q, u, -0.01583407049188512767371284);
+    q = fma_k(q, u, 0.01900090236519766360899345);
+    q = fma_k(q, u, -0.0234720319593868172360808);
+    q = fma_k(q, u, 0.03017832676360298774987899);
+    q = fma_k(q, u, -0.04115226337441031440928335);
+    q = fma_k(q, u, 0.06172839506164371309340048);
+    q = fma_k(q, u, -0.1111111111111111111111111);
+    return u * fma_k(u, q, 1.0 / 3.0);
 }
 
-// exp(t) - 1 for |t| <= 0.045: t (1 + t/2! + ... + t^7/8!) (the first
-// dropped term, t^9/9!, is below 2e-18).
-__device__ __forceinline__ double expm1_small(double t) {
-    double p = 1.0 / 40320.0;
-    p = fma3(p, t, 1.0 / 5040.0);
-    p = fma3(p, t, 1.0 / 720.0);
-    p = fma3(p, t, 1.0 / 120.0);
-    p = fma3(p, t, 1.0 / 24.0);
-    p = fma3(p, t, 1.0 / 6.0);
-    p = __builtin_fma(p, t, 0.5);
-    p = __builtin_fma(p, t, 1.0);
-    return t * p;
+// 3 ln(1+w) / w = 3 + w R3(w)
+__device__ __forceinline__ double log1p_cbrt_over_w(double w) {
+    double r = 0.4297688281944602466457629;
+    r = fma_k(r, w, -0.5002437143231824139713031);
+    r = fma_k(r, w, 0.599999539072323222208094);
+    r = fma_k(r, w, -0.7499999603441906901946652);
+    r = fma_k(r, w, 1.000000000035512911627931);
+    r = fma_k(r, w, -1.500000000000957520846056);
+    return fma_k(r, w, 3.0);
 }
 
 // The base of the stage logs and cube roots at the start of a step: within
 // a step the stage omegas stay close to omega_n, so with u = (w_s - w_n)/w_n
-//   ln|M w_s| = ln|M w_n| + ln(1 + u),
-//   (M w_s)^{1/3} = (M w_n)^{1/3} exp(ln(1 + u) / 3),
-// each from a short series; |u| > 1/8 (rejected or very long steps) falls
+//   (M w_s)^{1/3} = (M w_n)^{1/3} (1 + w),  w = (1 + u)^{1/3} - 1,
+//   ln|M w_s| = ln|M w_n| + 3 ln(1 + w),
+// each from a short polynomial; |u| > 1/16 (rejected or very long steps) falls
 // back to the full log and cube root.
 struct LogBase {
     double lnv;    // ln|M w_n|
@@ -250,8 +284,8 @@ struct LogBase {
     double iw;     // 1/w_n
 };
 
-// dy/dt of Eqs. (1)-(4) at y = (w, S1, S2, L) into d (d omega/dt in d[0]);
-// returns ln|M w| as used, and x = (M w)^{1/3} as used in xo.
+// dy/dt of Eqs. (1)-(4) at y = (w, S1, S2, L) into d (d omega/dt in d[0]),
+// given v = M w, x = v^{1/3} and ln|v|.
 //
 // With v = M w and x = v^{1/3}:
 //   d w/dt = K w^2 x^5 B (formed as K w^2 x^2 v B),
@@ -267,21 +301,10 @@ struct LogBase {
 // Off the physical region (stage points of rejected or fixed steps) omega may
 // be negative; x is then the real cube root and the log term uses
 // ln(16 x^2) = ln 16 + (2/3) ln|v|, which is what Eq. (1) gives for any real x.
-template <class RowT, bool FAST_LOG>
-__device__ __forceinline__ double rhs_x(const RowT& r, const TermConsts& tc, const LogBase& lb,
-                                        const double* __restrict__ y, double* __restrict__ d, double& xo) {
+template <class RowT>
+__device__ __forceinline__ void rhs_at(const RowT& r, const TermConsts& tc, const double* __restrict__ y,
+                                       double v, double x, double lnv, double* __restrict__ d) {
     const double w = y[0];
-    const double v = r[R_M] * w;
-    double x, lnv;
-    const double u = FAST_LOG ? (w - lb.w) * lb.iw : 1.0;
-    if (FAST_LOG && __builtin_fabs(u) <= 0.125) {
-        const double l1 = log1p_small(u);
-        lnv = lb.lnv + l1;
-        x = __builtin_fma(lb.x, expm1_small(l1 * (1.0 / 3.0)), lb.x);
-    } else {
-        x = cbrt_real(v);
-        lnv = log_pos(__builtin_fabs(v));
-    }
     const double x2 = x * x;
     const double L0 = y[7], L1 = y[8], L2 = y[9];
     const double a0 = y[1], a1 = y[2], a2 = y[3];   // S1
@@ -323,10 +346,40 @@ __device__ __forceinline__ double rhs_x(const RowT& r, const TermConsts& tc, con
     d[7] = q * (d[1] + d[4]);
     d[8] = q * (d[2] + d[5]);
     d[9] = q * (d[3] + d[6]);
+}
+
+// dy/dt at y into d; returns ln|M w| as used, and x = (M w)^{1/3} as used in
+// xo.  FAST_LOG: x and the log from the step's base point (LogBase).
+template <class RowT, bool FAST_LOG>
+__device__ __forceinline__ double rhs_x(const RowT& r, const TermConsts& tc, const LogBase& lb,
+                                        const double* __restrict__ y, double* __restrict__ d, double& xo) {
+    const double w = y[0];
+    const double v = r[R_M] * w;
+    double x, lnv;
+    if (FAST_LOG) {
+        // every lane takes the polynomials; the rare lanes with |u| > 1/16
+        // then redo x and the log in full, in a block the whole wave skips
+        // unless one of its lanes needs it
+        const double u = (w - lb.w) * lb.iw;
+        const double c = cbrt1p_small_m1(u);
+        x = __builtin_fma(lb.x, c, lb.x);
+        lnv = fma3(c, log1p_cbrt_over_w(c), lb.lnv);
+        const bool far = !(__builtin_fabs(u) <= kSmallU);
+        if (__builtin_expect(__ballot(far) != 0, 0)) {
+            if (far) {
+                x = cbrt_real(v);
+                lnv = log_pos(__builtin_fabs(v));
+            }
+        }
+        rhs_at(r, tc, y, v, x, lnv, d);
+    } else {
+        x = cbrt_real(v);
+        lnv = log_pos(__builtin_fabs(v));
+        rhs_at(r, tc, y, v, x, lnv, d);
+    }
     xo = x;
     return lnv;
 }
-
 template <class RowT, bool FAST_LOG>
 __device__ __forceinline__ double rhs(const RowT& r, const TermConsts& tc, const LogBase& lb,
                                       const double* __restrict__ y, double* __restrict__ d) {

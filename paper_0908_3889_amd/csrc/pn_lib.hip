@@ -152,7 +152,7 @@ __device__ __forceinline__ double error_norm(const Uni& u, const double* y, cons
     double z = 0.0;
 #pragma unroll
     for (int c = 0; c < 10; ++c) {
-        const double sc = __builtin_fma(u.tol, __builtin_fmax(__builtin_fabs(y[c]), __builtin_fabs(ynew[c])), u.tol);
+        const double sc = __builtin_fma(u.tol, fmax_abs(y[c], ynew[c]), u.tol);
         const double q = e[c] * rcp_1step(sc);
         z = __builtin_fma(q, q, z);
     }
@@ -224,9 +224,9 @@ __device__ __forceinline__ int control(const Uni& u, LaneT& L, bool go, int st, 
     // right after a rejection); one z^(-1/10) serves accepts and rejects
     double fac = 1.0;
     if (!fixed) {
-        const double p = 0.9 * pow_m_tenth(__builtin_fmin(__builtin_fmax(z, 9.313225746154785e-10), 1.073741824e9));
-        const double fa = __builtin_fmin(5.0, __builtin_fmax(0.2, p));
-        fac = rej ? __builtin_fmax(0.2, p) : (L.last_rej ? __builtin_fmin(fa, 1.0) : fa);
+        const double p = pow_m_tenth_scaled(fmin_k(fmax_k(z, 9.313225746154785e-10), 1.073741824e9), 0.9);
+        const double lo = fmax_k(p, 0.2);
+        fac = rej ? lo : fmin_k(lo, L.last_rej ? 1.0 : 5.0);
     }
     // The state is updated with selects rather than a divergent branch, so
     // that y and k1 keep their registers across the loop.
@@ -247,10 +247,12 @@ __device__ __forceinline__ int control(const Uni& u, LaneT& L, bool go, int st, 
     }
     const double tn = L.omega_mode ? __builtin_fma(h, (double)dts, L.t) : L.t + h;
     const bool done = take && (last || (!L.omega_mode && !tend && Y[0] == u.omega_f));
+    if (take) {
 #pragma unroll
-    for (int c = 0; c < 10; ++c) {
-        L.y[c] = take ? Y[c] : L.y[c];
-        L.k1[c] = take ? k7[c] : L.k1[c];
+        for (int c = 0; c < 10; ++c) {
+            L.y[c] = Y[c];
+            L.k1[c] = k7[c];
+        }
     }
     if (done && L.omega_mode) L.y[0] = u.omega_f;
     L.t = take ? tn : L.t;
@@ -349,14 +351,14 @@ struct F64 {
 #pragma unroll
             for (int c = 0; c < 10; ++c) Y[c] = __builtin_fma(c1, k1[c], y[c]);
             rhs<Row, true>(R, u.tc, lb, Y, k2);
-            if (any_w) to_omega_variable(k2, dtj, L.omega_mode);
+            if (__builtin_expect(any_w, 0)) to_omega_variable(k2, dtj, L.omega_mode);
         }
         {
             const double c1 = h * A31, c2 = h * A32;
 #pragma unroll
             for (int c = 0; c < 10; ++c) Y[c] = __builtin_fma(c2, k2[c], __builtin_fma(c1, k1[c], y[c]));
             rhs<Row, true>(R, u.tc, lb, Y, k3);
-            if (any_w) { to_omega_variable(k3, dtj, L.omega_mode); dts = __builtin_fma(B3, dtj, dts); }
+            if (__builtin_expect(any_w, 0)) { to_omega_variable(k3, dtj, L.omega_mode); dts = __builtin_fma(B3, dtj, dts); }
             if (PHASE) ps = __builtin_fma(B3, Y[0] * (any_w ? dtj : 1.0), ps);
         }
         {
@@ -365,7 +367,7 @@ struct F64 {
             for (int c = 0; c < 10; ++c)
                 Y[c] = __builtin_fma(c3, k3[c], __builtin_fma(c2, k2[c], __builtin_fma(c1, k1[c], y[c])));
             rhs<Row, true>(R, u.tc, lb, Y, k4);
-            if (any_w) { to_omega_variable(k4, dtj, L.omega_mode); dts = __builtin_fma(B4, dtj, dts); }
+            if (__builtin_expect(any_w, 0)) { to_omega_variable(k4, dtj, L.omega_mode); dts = __builtin_fma(B4, dtj, dts); }
             if (PHASE) ps = __builtin_fma(B4, Y[0] * (any_w ? dtj : 1.0), ps);
         }
         {
@@ -375,7 +377,7 @@ struct F64 {
                 Y[c] = __builtin_fma(c4, k4[c], __builtin_fma(c3, k3[c],
                        __builtin_fma(c2, k2[c], __builtin_fma(c1, k1[c], y[c]))));
             rhs<Row, true>(R, u.tc, lb, Y, k5);
-            if (any_w) { to_omega_variable(k5, dtj, L.omega_mode); dts = __builtin_fma(B5, dtj, dts); }
+            if (__builtin_expect(any_w, 0)) { to_omega_variable(k5, dtj, L.omega_mode); dts = __builtin_fma(B5, dtj, dts); }
             if (PHASE) ps = __builtin_fma(B5, Y[0] * (any_w ? dtj : 1.0), ps);
         }
         {
@@ -385,7 +387,7 @@ struct F64 {
                 Y[c] = __builtin_fma(c5, k5[c], __builtin_fma(c4, k4[c], __builtin_fma(c3, k3[c],
                        __builtin_fma(c2, k2[c], __builtin_fma(c1, k1[c], y[c])))));
             rhs<Row, true>(R, u.tc, lb, Y, k6);
-            if (any_w) { to_omega_variable(k6, dtj, L.omega_mode); dts = __builtin_fma(B6, dtj, dts); }
+            if (__builtin_expect(any_w, 0)) { to_omega_variable(k6, dtj, L.omega_mode); dts = __builtin_fma(B6, dtj, dts); }
             if (PHASE) ps = __builtin_fma(B6, Y[0] * (any_w ? dtj : 1.0), ps);
         }
         // stage 7 point = 5th-order solution; the error sum over k1, k3..k6 is
@@ -403,7 +405,7 @@ struct F64 {
         }
         double k7[10], dt7 = 1.0, x7;
         const double lnv7 = rhs_x<Row, true>(R, u.tc, lb, Y, k7, x7);
-        if (any_w) to_omega_variable(k7, dt7, L.omega_mode);
+        if (__builtin_expect(any_w, 0)) to_omega_variable(k7, dt7, L.omega_mode);
         L.nrhs += go ? 6 : 0;
 
         // the error norm is formed in fixed-step mode too (and ignored there),
@@ -495,14 +497,14 @@ struct F32Split {
 #pragma unroll
             for (int c = 0; c < 10; ++c) Y[c] = __builtin_fmaf(c1, k1[c], yf[c]);
             rhs_f32(R, u.tcf, Y, k2);
-            if (any_w) to_omega_variable(k2, dtj, L.omega_mode);
+            if (__builtin_expect(any_w, 0)) to_omega_variable(k2, dtj, L.omega_mode);
         }
         {
             const float c1 = hf * (float)A31, c2 = hf * (float)A32;
 #pragma unroll
             for (int c = 0; c < 10; ++c) Y[c] = __builtin_fmaf(c2, k2[c], __builtin_fmaf(c1, k1[c], yf[c]));
             rhs_f32(R, u.tcf, Y, k3);
-            if (any_w) { to_omega_variable(k3, dtj, L.omega_mode); dts = __builtin_fmaf((float)B3, dtj, dts); }
+            if (__builtin_expect(any_w, 0)) { to_omega_variable(k3, dtj, L.omega_mode); dts = __builtin_fmaf((float)B3, dtj, dts); }
             if (PHASE) ps = __builtin_fmaf((float)B3, Y[0] * (any_w ? dtj : 1.0f), ps);
         }
         {
@@ -511,7 +513,7 @@ struct F32Split {
             for (int c = 0; c < 10; ++c)
                 Y[c] = __builtin_fmaf(c3, k3[c], __builtin_fmaf(c2, k2[c], __builtin_fmaf(c1, k1[c], yf[c])));
             rhs_f32(R, u.tcf, Y, k4);
-            if (any_w) { to_omega_variable(k4, dtj, L.omega_mode); dts = __builtin_fmaf((float)B4, dtj, dts); }
+            if (__builtin_expect(any_w, 0)) { to_omega_variable(k4, dtj, L.omega_mode); dts = __builtin_fmaf((float)B4, dtj, dts); }
             if (PHASE) ps = __builtin_fmaf((float)B4, Y[0] * (any_w ? dtj : 1.0f), ps);
         }
         {
@@ -521,7 +523,7 @@ struct F32Split {
                 Y[c] = __builtin_fmaf(c4, k4[c], __builtin_fmaf(c3, k3[c],
                        __builtin_fmaf(c2, k2[c], __builtin_fmaf(c1, k1[c], yf[c]))));
             rhs_f32(R, u.tcf, Y, k5);
-            if (any_w) { to_omega_variable(k5, dtj, L.omega_mode); dts = __builtin_fmaf((float)B5, dtj, dts); }
+            if (__builtin_expect(any_w, 0)) { to_omega_variable(k5, dtj, L.omega_mode); dts = __builtin_fmaf((float)B5, dtj, dts); }
             if (PHASE) ps = __builtin_fmaf((float)B5, Y[0] * (any_w ? dtj : 1.0f), ps);
         }
         {
@@ -532,7 +534,7 @@ struct F32Split {
                 Y[c] = __builtin_fmaf(c5, k5[c], __builtin_fmaf(c4, k4[c], __builtin_fmaf(c3, k3[c],
                        __builtin_fmaf(c2, k2[c], __builtin_fmaf(c1, k1[c], yf[c])))));
             rhs_f32(R, u.tcf, Y, k6);
-            if (any_w) { to_omega_variable(k6, dtj, L.omega_mode); dts = __builtin_fmaf((float)B6, dtj, dts); }
+            if (__builtin_expect(any_w, 0)) { to_omega_variable(k6, dtj, L.omega_mode); dts = __builtin_fmaf((float)B6, dtj, dts); }
             if (PHASE) ps = __builtin_fmaf((float)B6, Y[0] * (any_w ? dtj : 1.0f), ps);
         }
         // 5th-order increment D (FP32), the stage-7 point, and the error sum
@@ -547,7 +549,7 @@ struct F32Split {
         }
         float k7[10], dt7 = 1.0f;
         rhs_f32(R, u.tcf, Y, k7);
-        if (any_w) to_omega_variable(k7, dt7, L.omega_mode);
+        if (__builtin_expect(any_w, 0)) to_omega_variable(k7, dt7, L.omega_mode);
         L.nrhs += go ? 6 : 0;
 
         // candidate state in FP64
