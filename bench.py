@@ -271,6 +271,26 @@ def leg_adjoint(api, population, stream, ks=(16, 64, 256), reps: int = 5, n: int
     return res
 
 
+def _ordered_run(api, pop, d, opts, out, stream, order: bool = True):
+    """One integration of the population, the longest-first hand-out order
+    (pn_cost_order) computed first when `order`."""
+    import torch
+    if not order:
+        api.set_order(opts, None)
+        return lambda: api.pn_integrate(d["m"], d["S"], d["L"], d["omega0"], pop["omega_f"], pop["tol"], opts,
+                                        out=out, stream=stream)
+    buf = torch.empty((pop["n"],), dtype=torch.int32, device="cuda")
+    ws = api.cost_order_workspace(pop["n"])
+    api.set_order(opts, buf)
+
+    def run():
+        api.pn_cost_order(d["m"], d["S"], d["L"], d["omega0"], pop["omega_f"], out=buf, workspace=ws,
+                          stream=stream)
+        api.pn_integrate(d["m"], d["S"], d["L"], d["omega0"], pop["omega_f"], pop["tol"], opts, out=out,
+                         stream=stream)
+    return run
+
+
 def leg_fp32split(api, pop, d, ref64: dict, stream, reps: int = 5) -> dict:
     """FP32-split on the same population as the FP64 run: time, fraction of
     the FP32 vector peak, and the error of every output against the FP64
@@ -278,8 +298,7 @@ def leg_fp32split(api, pop, d, ref64: dict, stream, reps: int = 5) -> dict:
     import torch
     opts = api.make_opts(precision="fp32split")
     out = api.alloc_outputs(pop["n"])
-    run = lambda: api.pn_integrate(d["m"], d["S"], d["L"], d["omega0"], pop["omega_f"], pop["tol"], opts,
-                                   out=out, stream=stream)
+    run = _ordered_run(api, pop, d, opts, out, stream)
     ms = _time_calls(run, reps, stream)
     g = {k: v.cpu().numpy() for k, v in out.items()}
     ok = (g["status"] == 0) & (ref64["status"] == 0)
@@ -318,24 +337,27 @@ def leg_fp32split(api, pop, d, ref64: dict, stream, reps: int = 5) -> dict:
 def leg_batching(api, population, stream, reps: int = 3, n: int | None = None) -> dict:
     """The batching workload (4,194,304 inspirals, omega0 log-uniform in
     [0.002, 0.01], q in [1, 10]): the persistent refill kernel against one
-    lane per inspiral without refill."""
+    lane per inspiral without refill (in index order), and the persistent
+    kernel with the inspirals handed out longest first (pn_cost_order,
+    timed with it)."""
     w = population.WORKLOADS["batching_4M"]
     pop = population.generate(w, n)
     d = api.to_device(pop)
     out = api.alloc_outputs(pop["n"])
     res = {"workload": w.name, "n": pop["n"]}
-    for sched in ("persistent", "static"):
+    for name, sched, order in (("persistent_cost_order", "persistent", True),
+                               ("persistent", "persistent", False), ("static", "static", False)):
         opts = api.make_opts(schedule=sched)
-        run = lambda: api.pn_integrate(d["m"], d["S"], d["L"], d["omega0"], pop["omega_f"], pop["tol"], opts,
-                                       out=out, stream=stream)
+        run = _ordered_run(api, pop, d, opts, out, stream, order)
         ms = _time_calls(run, reps, stream)
         steps = out["steps"].cpu().numpy()
-        res[sched] = {"ms": ms, "inspirals_per_s": pop["n"] / (ms * 1e-3),
-                      "frac": _frac(steps, ms, FP64_VECTOR_PEAK_TFLOPS),
-                      "status_ok": int((out["status"] == 0).sum().item())}
+        res[name] = {"ms": ms, "inspirals_per_s": pop["n"] / (ms * 1e-3),
+                     "frac": _frac(steps, ms, FP64_VECTOR_PEAK_TFLOPS),
+                     "status_ok": int((out["status"] == 0).sum().item())}
     acc = steps[0].astype(np.int64)
     res["accepted_steps_min_median_max"] = [int(acc.min()), int(np.median(acc)), int(acc.max())]
     res["static_over_persistent"] = res["static"]["ms"] / res["persistent"]["ms"]
+    res["static_over_persistent_cost_order"] = res["static"]["ms"] / res["persistent_cost_order"]["ms"]
     return res
 
 
@@ -491,6 +513,9 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="q1to4_1M")
     ap.add_argument("--schedule", default="persistent", choices=["persistent", "static"])
+    ap.add_argument("--order", default="cost", choices=["cost", "natural"],
+                    help="hand the inspirals to lanes longest first (pn_cost_order, timed as part of "
+                         "every step) or in index order")
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--waves-per-simd", type=int, default=0)
     ap.add_argument("--refill-min", type=int, default=0)
@@ -557,9 +582,25 @@ def main() -> int:
                  "table_ms": {f"{r},{b}": v for (r, b), v in table.items()}}
 
     integrate = api.pn_integrate_phase if args.phase else api.pn_integrate
+    # the longest-first hand-out order, recomputed inside every timed step
+    cost_order = args.order == "cost" and args.schedule == "persistent"
+    order_buf = torch.empty((pop["n"],), dtype=torch.int32, device="cuda") if cost_order else None
+    order_ws = api.cost_order_workspace(pop["n"]) if cost_order else None
+    api.set_order(opts, order_buf)
 
-    def step():
+    def step(kev=None):
+        """One pass over the workload; kev: a list that receives the HIP
+        events around the integration kernel alone (the dominant kernel)."""
+        if cost_order:
+            api.pn_cost_order(d["m"], d["S"], d["L"], d["omega0"], pop["omega_f"], out=order_buf,
+                              workspace=order_ws, stream=stream)
+        if kev is not None:
+            kev.append(torch.cuda.Event(enable_timing=True))
+            kev[-1].record(stream)
         integrate(d["m"], d["S"], d["L"], d["omega0"], pop["omega_f"], pop["tol"], opts, out=out, stream=stream)
+        if kev is not None:
+            kev.append(torch.cuda.Event(enable_timing=True))
+            kev[-1].record(stream)
 
     if args.adjoint:
         return bench_adjoint(args, api, pop, d, w, step, stream)
@@ -573,15 +614,16 @@ def main() -> int:
     starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
     ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
     torch.cuda.synchronize()
+    kev = []
     t0 = time.perf_counter()
     for k in range(args.steps):
         starts[k].record(stream)
-        step()
+        step(kev)
         ends[k].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    kernel_ms = [s.elapsed_time(e) for s, e in zip(starts, ends)]
-    avg_ms = float(np.mean(kernel_ms))
+    step_ms = float(np.mean([s.elapsed_time(e) for s, e in zip(starts, ends)]))
+    avg_ms = float(np.mean([kev[2 * k].elapsed_time(kev[2 * k + 1]) for k in range(args.steps)]))
 
     steps = out["steps"].cpu().numpy()
     status = out["status"].cpu().numpy()
@@ -627,6 +669,8 @@ def main() -> int:
         "launch": {"block": opts.block or 256, "refill_min": opts.refill_min or 4,
                    "waves_per_simd": opts.waves_per_simd or None, "autotuned": tuned},
         "kernel_ms": avg_ms,
+        "step_ms_events": step_ms,
+        "order": "cost (pn_cost_order inside every step)" if cost_order else "natural",
         "rhs_evals_per_s": float(steps[2].astype(np.int64).sum()) / (avg_ms * 1e-3),
         "attempted_steps": attempted_steps(steps),
         "accepted_steps": int(steps[0].astype(np.int64).sum()),

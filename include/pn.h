@@ -118,6 +118,15 @@ typedef struct pn_opts {
                               costs the whole wave, so refilling in small batches
                               beats refilling every lane at once) */
     int32_t precision;     /* PN_PREC_*; 0 -> FP64 */
+    const int32_t* order;  /* NULL, or device int32 [n]: the inspiral indices in the
+                              order in which the schedule hands them to lanes (a
+                              permutation of 0 .. n-1, e.g. from pn_cost_order).
+                              Every output is written at the inspiral's own index,
+                              so the results do not depend on the order, only the
+                              speed does.  Entries outside [0, n) are skipped (that
+                              slot integrates nothing); an index missing from the
+                              array leaves its outputs unwritten.  Requires
+                              n <= 2^31 - 1. */
 } pn_opts;
 
 /*
@@ -150,6 +159,36 @@ int pn_integrate(int64_t n, int64_t ld,
                  double omega_f, double tol, const pn_opts* opt,
                  double* y_final, double* t_final, int32_t* steps, int32_t* status,
                  double* dots, void* stream);
+
+/*
+ * pn_cost_order -- an order in which to hand the inspirals to lanes (for
+ * pn_opts.order): longest first, by a leading-order estimate of each
+ * inspiral's number of steps.  Lanes of a wave step together, and once every
+ * inspiral has been handed out the waves drain while the last ones finish;
+ * with the longest handed out first the drain is made of short ones
+ * (Sec. IV: throughput depends on how evenly the work is spread).  The
+ * estimate: an adaptive 5th-order method needs about the integral of
+ * |d^5 y/dt^5|^(1/5) dt steps; a spin precessing at rate Omega_i with
+ * amplitude a_i contributes a_i^(1/5) Omega_i to the integrand, and the
+ * leading-order precession angle (the L_hat part of Eq. (4) over the
+ * Newtonian chirp of Eq. (1)) from omega0 to omega_f is proportional to
+ * (4 + 3 m_j/m_i)(1/omega0 - 1/omega_f)/M.  The key is the larger of the two
+ * spins' a_i^(1/5) times that angle, a_i being the component of S_i normal
+ * to the initial total angular momentum.  Inspirals that end at once
+ * (omega0 >= omega_f) or that the integrator refuses come last.  Equal keys
+ * keep their index order.
+ * Inputs as pn_integrate (device, SoA, leading dimension ld); omega_f <= 0
+ * ranks by 1/omega0 alone.  order [n]: device int32 output, a permutation of
+ * 0 .. n-1.  workspace: device scratch of at least
+ * pn_cost_order_workspace_bytes(n) bytes, caller-owned.  Requires
+ * n <= 2^31 - 1; PN_EINVAL for bad sizes, NULL pointers or a small
+ * workspace.  The ranking only changes the speed of pn_integrate, never its
+ * results.
+ */
+size_t pn_cost_order_workspace_bytes(int64_t n);
+int pn_cost_order(int64_t n, int64_t ld, const double* m, const double* S0, const double* L0,
+                  const double* omega0, double omega_f, int32_t* order, void* workspace,
+                  size_t ws_bytes, void* stream);
 
 /*
  * pn_integrate_noalloc -- pn_integrate for callers that cannot allocate

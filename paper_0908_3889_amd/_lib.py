@@ -28,7 +28,7 @@ EXPORTS = ("pn_integrate", "pn_rhs", "pn_observables", "pn_strerror", "pn_versio
            "pn_tape_stride", "pn_integrate_record", "pn_adjoint_workspace_bytes",
            "pn_integrate_adjoint", "pn_histogram", "pn_histogram2d", "pn_pearson", "pn_kde",
            "pn_ks_workspace_bytes", "pn_ks_uniform", "pn_stats_workspace_bytes", "pn_generate",
-           "pn_autotune", "pn_integrate_phase", "pn_fma_rate", "pn_shutdown", "pn_integrate_noalloc")
+           "pn_autotune", "pn_integrate_phase", "pn_fma_rate", "pn_shutdown", "pn_integrate_noalloc", "pn_cost_order", "pn_cost_order_workspace_bytes")
 
 
 class PnOpts(C.Structure):
@@ -44,6 +44,7 @@ class PnOpts(C.Structure):
         ("waves_per_simd", C.c_int32),
         ("refill_min", C.c_int32),
         ("precision", C.c_int32),
+        ("order", C.c_void_p),
     ]
 
 
@@ -73,6 +74,10 @@ def load():
     popts = C.POINTER(PnOpts)
     L.pn_integrate.argtypes = [i64, i64, vp, vp, vp, vp, dbl, dbl, popts, vp, vp, vp, vp, vp, vp]
     L.pn_integrate.restype = C.c_int
+    L.pn_cost_order_workspace_bytes.argtypes = [i64]
+    L.pn_cost_order_workspace_bytes.restype = C.c_size_t
+    L.pn_cost_order.argtypes = [i64, i64, vp, vp, vp, vp, dbl, vp, vp, C.c_size_t, vp]
+    L.pn_cost_order.restype = C.c_int
     L.pn_integrate_noalloc.argtypes = [i64, i64, vp, vp, vp, vp, dbl, dbl, popts, vp, vp, vp, vp, vp, vp]
     L.pn_integrate_noalloc.restype = C.c_int
     L.pn_integrate_phase.argtypes = [i64, i64, vp, vp, vp, vp, dbl, dbl, popts, vp, vp, vp, vp, vp, vp, vp]

@@ -52,14 +52,58 @@ def _stream(stream):
 
 def make_opts(*, h0=0.0, h_fixed=0.0, t_end=0.0, max_steps=0, terms=_lib.PN_TERM_ALL,
               theta_literal=0, schedule="persistent", block=0, waves_per_simd=0,
-              refill_min=0, precision="fp64") -> PnOpts:
+              refill_min=0, precision="fp64", order=None) -> PnOpts:
+    """pn_opts; order: None or an int32 device tensor [n] (pn_cost_order),
+    kept alive by the returned struct."""
     o = PnOpts()
     o.h0, o.h_fixed, o.t_end = float(h0), float(h_fixed), float(t_end)
     o.max_steps, o.terms, o.theta_literal = int(max_steps), int(terms), int(theta_literal)
     o.schedule = SCHEDULES[schedule] if isinstance(schedule, str) else int(schedule)
     o.block, o.waves_per_simd, o.refill_min = int(block), int(waves_per_simd), int(refill_min)
     o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    set_order(o, order)
     return o
+
+
+def set_order(o: PnOpts, order) -> PnOpts:
+    """Point o.order at an int32 device tensor (or clear it with None)."""
+    if order is None:
+        o.order = None
+        o._order_ref = None
+        return o
+    if order.dtype != torch.int32 or order.dim() != 1 or not order.is_contiguous():
+        raise ValueError("order must be a contiguous 1-d int32 tensor")
+    o.order = C.c_void_p(order.data_ptr())
+    o._order_ref = order
+    return o
+
+
+def cost_order_workspace(n: int, device=None):
+    """A device workspace tensor for pn_cost_order on n inspirals."""
+    b = int(load().pn_cost_order_workspace_bytes(int(n)))
+    dev = device or torch.device("cuda", torch.cuda.current_device())
+    return torch.empty((max(b, 1),), dtype=torch.uint8, device=dev)
+
+
+def pn_cost_order(m, S0, L0, omega0, omega_f, out=None, workspace=None, stream=None):
+    """The longest-first hand-out order of the inspirals (int32 [n] on the
+    device) from the leading-order step estimate of pn_cost_order."""
+    n = int(omega0.shape[0])
+    _soa(omega0, 1, n, "omega0")
+    _soa(m, 2, n, "m"); _soa(S0, 6, n, "S0"); _soa(L0, 3, n, "L0")
+    lds = {_ld(m, n), _ld(S0, n), _ld(L0, n)}
+    if n > 0 and len(lds) != 1:
+        raise ValueError("all [components, n] arrays must share one leading dimension")
+    ld = lds.pop() if n > 0 else 0
+    if out is None:
+        out = torch.empty((n,), dtype=torch.int32, device=omega0.device)
+    if workspace is None:
+        workspace = cost_order_workspace(n, omega0.device)
+    p = lambda t: C.c_void_p(t.data_ptr())
+    rc = load().pn_cost_order(n, ld, p(m), p(S0), p(L0), p(omega0), float(omega_f), p(out), p(workspace),
+                              int(workspace.numel()), _stream(stream))
+    check(rc, "pn_cost_order")
+    return out
 
 
 def alloc_outputs(n: int, device=None, dots: bool = True) -> dict:

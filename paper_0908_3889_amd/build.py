@@ -22,7 +22,8 @@ LIB = os.path.join(HERE, "libpn.so")
 RESOURCE_REPORT = os.path.join(HERE, "build_resource_usage.txt")
 
 SOURCES = [os.path.join(CSRC, "pn_lib.hip"), os.path.join(CSRC, "pn_stats.hip"),
-           os.path.join(CSRC, "pn_generate.hip"), os.path.join(CSRC, "pn_probe.hip")]
+           os.path.join(CSRC, "pn_generate.hip"), os.path.join(CSRC, "pn_probe.hip"),
+           os.path.join(CSRC, "pn_order.hip")]
 
 
 def hipcc() -> str:

@@ -79,6 +79,7 @@ struct Io {
     int32_t* __restrict__ status;
     double* __restrict__ dots;
     double* __restrict__ phase;   // orbital phase at t_final, or null
+    const int32_t* __restrict__ order;   // hand-out order of the inspirals, or null
 };
 
 // What a persistent launch reads only when it refills lanes or writes
@@ -627,10 +628,15 @@ __device__ __forceinline__ void persistent_loop(const Uni& u, unsigned long long
                 if (!active) {
                     const unsigned rank = __builtin_amdgcn_mbcnt_hi((unsigned)(need >> 32),
                                           __builtin_amdgcn_mbcnt_lo((unsigned)need, 0u));
-                    const unsigned long long idx = base + rank;
-                    if (idx < (unsigned long long)u.n) {
-                        const int st = P::load(io, uc, L, (int64_t)idx);
-                        if (st == 0) active = true; else still = true;
+                    const unsigned long long pos = base + rank;
+                    if (pos < (unsigned long long)u.n) {
+                        const int64_t idx = io.order ? (int64_t)io.order[pos] : (int64_t)pos;
+                        if (idx >= 0 && idx < u.n) {
+                            const int st = P::load(io, uc, L, idx);
+                            if (st == 0) active = true; else still = true;
+                        } else {
+                            still = true;      // not an index: this slot integrates nothing
+                        }
                     }
                 }
                 if (base + cnt >= (unsigned long long)u.n) exhausted = true;
@@ -653,11 +659,14 @@ __device__ __forceinline__ void persistent_loop(const Uni& u, unsigned long long
 
 // One lane per inspiral, no refill: a wave runs until its longest inspiral ends.
 template <class P>
-__device__ __forceinline__ void static_loop(const Io& io, const Uni& u, int64_t idx) {
+__device__ __forceinline__ void static_loop(const Io& io, const Uni& u, int64_t pos) {
     typename P::LaneT L{};
     L.y[0] = 1.0;
     bool active = false;
-    if (idx < u.n) active = P::load(io, u, L, idx) == 0;
+    if (pos < u.n) {
+        const int64_t idx = io.order ? (int64_t)io.order[pos] : pos;
+        if (idx >= 0 && idx < u.n) active = P::load(io, u, L, idx) == 0;
+    }
     for (;;) {
         if (wave_ballot(active) == 0) break;
         const bool any_w = wave_ballot(active && L.omega_mode) != 0;
@@ -1321,6 +1330,7 @@ static int integrate_impl(int64_t n, int64_t ld, const double* m, const double* 
     if (refill < 1 || refill > 64) return PN_EINVAL;
     if (o.terms < 0 || o.terms > PN_TERM_ALL) return PN_EINVAL;
     if (o.theta_literal != 0 && o.theta_literal != 1) return PN_EINVAL;
+    if (o.order && n > INT32_MAX) return PN_EINVAL;
     if (tape) {
         if (o.precision != PN_PREC_FP64 || tend) return PN_EINVAL;
         if (cap_steps < 1 || cap_steps > (1 << 28) || ckpt_every < 1 || ckpt_every > 4096) return PN_EINVAL;
@@ -1359,6 +1369,7 @@ static int integrate_impl(int64_t n, int64_t ld, const double* m, const double* 
     io.m = m; io.S0 = S0; io.L0 = L0; io.w0 = omega0;
     io.y = y_final; io.t = t_final; io.steps = steps; io.status = status; io.dots = dots;
     io.phase = phase;
+    io.order = o.order;
 
     hipStream_t s = (hipStream_t)stream;
     if (o.schedule == PN_SCHED_STATIC) {

@@ -44,8 +44,9 @@ def test_strerror_and_version(lib):
 
 def test_opts_struct_layout_matches_header():
     from paper_0908_3889_amd._lib import PnOpts
-    # 3 doubles, one int64, seven int32, padded to 8 bytes
-    assert C.sizeof(PnOpts) == 3 * 8 + 8 + 7 * 4 + 4
+    # 3 doubles, one int64, seven int32 padded to 8 bytes, one pointer
+    assert C.sizeof(PnOpts) == 3 * 8 + 8 + 7 * 4 + 4 + 8
+    assert PnOpts.order.offset == 64
     names = [f[0] for f in PnOpts._fields_]
     src = open(os.path.join(ROOT, "include", "pn.h")).read()
     body = src[src.index("typedef struct pn_opts"):src.index("} pn_opts;")]
@@ -96,3 +97,20 @@ def test_invalid_arguments_return_einval_without_a_device(lib):
     assert lib.pn_rhs(-1, 0, fake, fake, fake, None, z) == PN_EINVAL
     assert lib.pn_observables(5, 4, fake, fake, z) == PN_EINVAL
     assert lib.pn_observables(0, 0, fake, fake, z) == PN_OK
+
+
+def test_cost_order_argument_checks_without_a_device(lib):
+    from paper_0908_3889_amd._lib import PN_EINVAL, PN_OK
+    fake = C.c_void_p(0x1000)       # never dereferenced: validation fails first
+    z = C.c_void_p(0)
+    assert lib.pn_cost_order_workspace_bytes(0) == 0
+    assert lib.pn_cost_order_workspace_bytes(-1) == 0
+    assert lib.pn_cost_order_workspace_bytes(1 << 31) == 0
+    call = lambda n, ld, ptr=fake, ws=1 << 20, wf=0.05: lib.pn_cost_order(
+        n, ld, ptr, ptr, ptr, ptr, wf, ptr, ptr, ws, z)
+    assert call(-1, 0) == PN_EINVAL
+    assert call(10, 5) == PN_EINVAL
+    assert call(1 << 31, 1 << 31) == PN_EINVAL
+    assert call(10, 10, wf=float("nan")) == PN_EINVAL
+    assert call(10, 10, ptr=z) == PN_EINVAL
+    assert call(0, 0, ptr=z) == PN_OK
