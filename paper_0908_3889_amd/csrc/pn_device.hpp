@@ -348,6 +348,23 @@ __device__ __forceinline__ void rhs_at(const RowT& r, const TermConsts& tc, cons
     d[9] = q * (d[3] + d[6]);
 }
 
+// x = v^{1/3} and ln|v| at a stage point (v = M w) from the step's base
+// point: the polynomials in u = (w - w_n)/w_n, or in full on the rare lanes
+// with |u| > 1/16 (a block the wave skips unless one of its lanes needs it).
+__device__ __forceinline__ void stage_x_lnv(const LogBase& lb, double v, double w, double& x, double& lnv) {
+    const double u = (w - lb.w) * lb.iw;
+    const double c = cbrt1p_small_m1(u);
+    x = __builtin_fma(lb.x, c, lb.x);
+    lnv = fma3(c, log1p_cbrt_over_w(c), lb.lnv);
+    const bool far = !(__builtin_fabs(u) <= kSmallU);
+    if (__builtin_expect(__ballot(far) != 0, 0)) {
+        if (far) {
+            x = cbrt_real(v);
+            lnv = log_pos(__builtin_fabs(v));
+        }
+    }
+}
+
 // dy/dt at y into d; returns ln|M w| as used, and x = (M w)^{1/3} as used in
 // xo.  FAST_LOG: x and the log from the step's base point (LogBase).
 template <class RowT, bool FAST_LOG>
@@ -357,20 +374,7 @@ __device__ __forceinline__ double rhs_x(const RowT& r, const TermConsts& tc, con
     const double v = r[R_M] * w;
     double x, lnv;
     if (FAST_LOG) {
-        // every lane takes the polynomials; the rare lanes with |u| > 1/16
-        // then redo x and the log in full, in a block the whole wave skips
-        // unless one of its lanes needs it
-        const double u = (w - lb.w) * lb.iw;
-        const double c = cbrt1p_small_m1(u);
-        x = __builtin_fma(lb.x, c, lb.x);
-        lnv = fma3(c, log1p_cbrt_over_w(c), lb.lnv);
-        const bool far = !(__builtin_fabs(u) <= kSmallU);
-        if (__builtin_expect(__ballot(far) != 0, 0)) {
-            if (far) {
-                x = cbrt_real(v);
-                lnv = log_pos(__builtin_fabs(v));
-            }
-        }
+        stage_x_lnv(lb, v, w, x, lnv);
         rhs_at(r, tc, y, v, x, lnv, d);
     } else {
         x = cbrt_real(v);

@@ -776,11 +776,11 @@ struct AdjIo {
     const int32_t* __restrict__ order;  // [n] or null
 };
 
-// the stage derivative: f (time mode) or g (omega mode)
-__device__ __forceinline__ void stage_deriv(const Row& R, const TermConsts& tc, const double* Y, double* k,
-                                            bool om) {
-    const LogBase lb{};
-    rhs<Row, false>(R, tc, lb, Y, k);
+// the stage derivative: f (time mode) or g (omega mode); the cube root and
+// log of the stage from the step's base point lb
+__device__ __forceinline__ void stage_deriv(const Row& R, const TermConsts& tc, const LogBase& lb, const double* Y,
+                                            double* k, bool om) {
+    rhs<Row, true>(R, tc, lb, Y, k);
     if (om) {
         const double s = 1.0 / k[0];
 #pragma unroll
@@ -792,32 +792,33 @@ __device__ __forceinline__ void stage_deriv(const Row& R, const TermConsts& tc, 
 // one replayed step (no error control): y <- y + h sum b_i k_i
 __device__ __forceinline__ void replay_step(const Row& R, const TermConsts& tc, double* y, double h, bool om) {
     double k1[10], k2[10], k3[10], k4[10], k5[10], k6[10], Y[10];
-    stage_deriv(R, tc, y, k1, om);
+    const LogBase lb = log_base(R, y);
+    stage_deriv(R, tc, lb, y, k1, om);
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int c = 0; c < 10; ++c) Y[c] = __builtin_fma(h * A21, k1[c], y[c]);
-    stage_deriv(R, tc, Y, k2, om);
+    stage_deriv(R, tc, lb, Y, k2, om);
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int c = 0; c < 10; ++c) Y[c] = __builtin_fma(h * A32, k2[c], __builtin_fma(h * A31, k1[c], y[c]));
-    stage_deriv(R, tc, Y, k3, om);
+    stage_deriv(R, tc, lb, Y, k3, om);
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int c = 0; c < 10; ++c)
         Y[c] = __builtin_fma(h * A43, k3[c], __builtin_fma(h * A42, k2[c], __builtin_fma(h * A41, k1[c], y[c])));
-    stage_deriv(R, tc, Y, k4, om);
+    stage_deriv(R, tc, lb, Y, k4, om);
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int c = 0; c < 10; ++c)
         Y[c] = __builtin_fma(h * A54, k4[c], __builtin_fma(h * A53, k3[c],
                __builtin_fma(h * A52, k2[c], __builtin_fma(h * A51, k1[c], y[c]))));
-    stage_deriv(R, tc, Y, k5, om);
+    stage_deriv(R, tc, lb, Y, k5, om);
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int c = 0; c < 10; ++c)
         Y[c] = __builtin_fma(h * A65, k5[c], __builtin_fma(h * A64, k4[c], __builtin_fma(h * A63, k3[c],
                __builtin_fma(h * A62, k2[c], __builtin_fma(h * A61, k1[c], y[c])))));
-    stage_deriv(R, tc, Y, k6, om);
+    stage_deriv(R, tc, lb, Y, k6, om);
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int c = 0; c < 10; ++c)
@@ -854,25 +855,26 @@ __device__ __forceinline__ void reverse_step(const Row& R, const TermConsts& tc,
 #pragma unroll
         for (int c = 0; c < 11; ++c) nxt[c] = pf[c * pfstride];
         double k1[10], k2[10], k3[10], k4[10], k5[10], Y[10];
-        stage_deriv(R, tc, y, k1, om);
+        const LogBase lbs = log_base(R, y);
+        stage_deriv(R, tc, lbs, y, k1, om);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int c = 0; c < 10; ++c) { Y[c] = __builtin_fma(h * A21, k1[c], y[c]); YS(1, c) = Y[c]; }
-        stage_deriv(R, tc, Y, k2, om);
+        stage_deriv(R, tc, lbs, Y, k2, om);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int c = 0; c < 10; ++c) {
             Y[c] = __builtin_fma(h * A32, k2[c], __builtin_fma(h * A31, k1[c], y[c]));
             YS(2, c) = Y[c];
         }
-        stage_deriv(R, tc, Y, k3, om);
+        stage_deriv(R, tc, lbs, Y, k3, om);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int c = 0; c < 10; ++c) {
             Y[c] = __builtin_fma(h * A43, k3[c], __builtin_fma(h * A42, k2[c], __builtin_fma(h * A41, k1[c], y[c])));
             YS(3, c) = Y[c];
         }
-        stage_deriv(R, tc, Y, k4, om);
+        stage_deriv(R, tc, lbs, Y, k4, om);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int c = 0; c < 10; ++c) {
@@ -880,7 +882,7 @@ __device__ __forceinline__ void reverse_step(const Row& R, const TermConsts& tc,
                    __builtin_fma(h * A52, k2[c], __builtin_fma(h * A51, k1[c], y[c]))));
             YS(4, c) = Y[c];
         }
-        stage_deriv(R, tc, Y, k5, om);
+        stage_deriv(R, tc, lbs, Y, k5, om);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int c = 0; c < 10; ++c)
