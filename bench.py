@@ -166,7 +166,9 @@ def kernel_resources(kernel: str, block: int):
     want = {"integrate_persistent_f64": f"integrate_persistent_f64ILi{block}ELb0E",
             "integrate_persistent_f32s": f"integrate_persistent_f32sILi{block}E",
             "integrate_static_f64": f"integrate_static_f64ILi{block}ELb0E",
-            "integrate_static_f32s": f"integrate_static_f32sILi{block}E"}.get(kernel)
+            "integrate_static_f32s": f"integrate_static_f32sILi{block}E",
+            "integrate_persistent_f32x": f"integrate_persistent_f32xILi{block}E",
+            "integrate_static_f32x": f"integrate_static_f32xILi{block}E"}.get(kernel)
     if kernel.endswith("_phase"):
         want = f"{kernel}ILi{block}E"
     for name, fields in build.resource_usage().items():
@@ -291,12 +293,14 @@ def _ordered_run(api, pop, d, opts, out, stream, order: bool = True):
     return run
 
 
-def leg_fp32split(api, pop, d, ref64: dict, stream, reps: int = 5) -> dict:
-    """FP32-split on the same population as the FP64 run: time, fraction of
-    the FP32 vector peak, and the error of every output against the FP64
-    path (which the CPU-baseline leg checks against the oracle)."""
+def leg_fp32split(api, pop, d, ref64: dict, stream, reps: int = 5, precision: str = "fp32split") -> dict:
+    """An FP32 mode (FP32-split: FP64 state; "fp32": FP32 state with
+    compensated omega and phase) on the same population as the FP64 run:
+    time, fraction of the FP32 vector peak, and the error of every output
+    against the FP64 path (which the CPU-baseline leg checks against the
+    oracle)."""
     import torch
-    opts = api.make_opts(precision="fp32split")
+    opts = api.make_opts(precision=precision)
     out = api.alloc_outputs(pop["n"])
     run = _ordered_run(api, pop, d, opts, out, stream)
     ms = _time_calls(run, reps, stream)
@@ -318,6 +322,7 @@ def leg_fp32split(api, pop, d, ref64: dict, stream, reps: int = 5) -> dict:
         "t (relative)": _stats(np.abs(g["t"][ok] / ref64["t"][ok] - 1)),
     }
     # the orbital phase, integrated alongside in both precisions (untimed)
+    api.set_order(opts, None)
     p32 = api.pn_integrate_phase(d["m"], d["S"], d["L"], d["omega0"], pop["omega_f"], pop["tol"], opts,
                                  stream=stream)
     p64 = api.pn_integrate_phase(d["m"], d["S"], d["L"], d["omega0"], pop["omega_f"], pop["tol"],
@@ -519,7 +524,7 @@ def main() -> int:
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--waves-per-simd", type=int, default=0)
     ap.add_argument("--refill-min", type=int, default=0)
-    ap.add_argument("--precision", default=None, choices=["fp64", "fp32split"],
+    ap.add_argument("--precision", default=None, choices=["fp64", "fp32split", "fp32"],
                     help="default: the workload's own precision")
     ap.add_argument("--adjoint", default=None,
                     help="comma-separated checkpoint spacings K: time the recorded forward and the "
@@ -635,7 +640,8 @@ def main() -> int:
     peak = FP64_VECTOR_PEAK_TFLOPS if precision == "fp64" else FP32_VECTOR_PEAK_TFLOPS
     n = pop["n"]
     value = n * args.steps / wall
-    kernel = f"integrate_{args.schedule}_{'f64' if precision == 'fp64' else 'f32s'}" + ("_phase" if args.phase else "")
+    kernel = (f"integrate_{args.schedule}_{ {'fp64': 'f64', 'fp32split': 'f32s', 'fp32': 'f32x'}[precision] }"
+              + ("_phase" if args.phase else ""))
     traffic = measured_traffic(kernel, w.name)
     resources = kernel_resources(kernel, opts.block or 256)
     res = {
@@ -649,7 +655,8 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if precision == "fp64" else "f32 stages + f64 state/control",
+        "dtype": {"fp64": "f64", "fp32split": "f32 stages + f64 state/control",
+                  "fp32": "f32 state/stages (compensated omega) + f64 control"}[precision],
         "data": "synthetic",
         "config": {"workload": w.name, "n": n, "tol": w.tol, "omega0": list(w.omega0[1:]),
                    "omega_f": w.omega_f, "q": list(w.q[1:]), "chi": list(w.chi[1:]),
@@ -700,6 +707,7 @@ def main() -> int:
         ref64 = {k: v.cpu().numpy() for k, v in out.items() if v is not None}
         res["adjoint"] = leg_adjoint(api, population, stream)
         res["fp32split"] = leg_fp32split(api, pop, d, ref64, stream)
+        res["fp32_state"] = leg_fp32split(api, pop, d, ref64, stream, precision="fp32")
         res["batching"] = leg_batching(api, population, stream)
     if not args.no_cpu_baseline:
         gpu = {"dots": out["dots"].cpu().numpy(), "steps": steps, "status": status}

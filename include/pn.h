@@ -93,6 +93,13 @@ extern "C" {
                                   (the FP32 increment is added to the FP64 state);
                                   the paper ran its GPU in single precision with a
                                   few computations in double (Sec. III) */
+#define PN_PREC_FP32_STATE  2  /* as PN_PREC_FP32_SPLIT, but the state too is FP32:
+                                  omega as a float plus the summed rounding of its
+                                  increments (compensated summation, about 48
+                                  bits), S1, S2, L_hat as floats; the phase of
+                                  pn_integrate_phase is summed the same way; t, h,
+                                  the error norm, the step control and the
+                                  omega >= omega_f test stay FP64 */
 
 /* ---- scheduling -------------------------------------------------------- */
 #define PN_SCHED_PERSISTENT 0  /* resident grid; lanes take new inspirals as theirs finish */

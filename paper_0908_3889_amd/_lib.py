@@ -22,7 +22,7 @@ PN_TERM_PN, PN_TERM_SO_WDOT, PN_TERM_SS_WDOT, PN_TERM_RR = 1, 2, 4, 8
 PN_TERM_SO_PREC, PN_TERM_SS_PREC, PN_TERM_ALL = 16, 32, 63
 # schedules and arithmetic
 PN_SCHED_PERSISTENT, PN_SCHED_STATIC = 0, 1
-PN_PREC_FP64, PN_PREC_FP32_SPLIT = 0, 1
+PN_PREC_FP64, PN_PREC_FP32_SPLIT, PN_PREC_FP32_STATE = 0, 1, 2
 
 EXPORTS = ("pn_integrate", "pn_rhs", "pn_observables", "pn_strerror", "pn_version",
            "pn_tape_stride", "pn_integrate_record", "pn_adjoint_workspace_bytes",

@@ -16,7 +16,7 @@ from . import _lib
 from ._lib import PnOpts, check, load
 
 SCHEDULES = {"persistent": _lib.PN_SCHED_PERSISTENT, "static": _lib.PN_SCHED_STATIC}
-PRECISIONS = {"fp64": _lib.PN_PREC_FP64, "fp32split": _lib.PN_PREC_FP32_SPLIT}
+PRECISIONS = {"fp64": _lib.PN_PREC_FP64, "fp32split": _lib.PN_PREC_FP32_SPLIT, "fp32": _lib.PN_PREC_FP32_STATE}
 
 
 def _on_current_device(t: torch.Tensor, name: str) -> None:

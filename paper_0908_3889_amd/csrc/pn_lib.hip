@@ -31,6 +31,10 @@ namespace pn {
 // for; chosen by measurement (register budget 512/target per lane).
 constexpr int kWpeF64 = 2;
 constexpr int kWpeF32 = 3;
+#ifndef PN_WPE_F32S
+#define PN_WPE_F32S 3
+#endif
+constexpr int kWpeF32S = PN_WPE_F32S;
 
 // ---------------------------------------------------------------------------
 // Dormand-Prince RK5(4)7M tableau (Dormand & Prince 1980)
@@ -200,7 +204,7 @@ __device__ __forceinline__ int pre_status(const Uni& u, const LaneT& L) {
 // fixed step, no t_end), so those tests fold away.
 template <bool GEN, class LaneT>
 __device__ __forceinline__ double clip_step(const Uni& u, const LaneT& L, bool& last) {
-    const double remain = L.omega_mode ? u.omega_f - L.y[0] : (GEN ? u.t_end - L.t : 0.0);
+    const double remain = L.omega_mode ? u.omega_f - L.omega() : (GEN ? u.t_end - L.t : 0.0);
     last = (L.omega_mode || (GEN && u.tend)) && L.h >= remain;
     return last ? remain : L.h;
 }
@@ -238,7 +242,7 @@ __device__ __forceinline__ int control(const Uni& u, LaneT& L, bool go, int st, 
         L.k1[0] = to_w ? KT(1) : L.k1[0];
         L.dt1 = to_w ? s : L.dt1;
         L.nt = to_w ? L.acc : L.nt;
-        L.h = to_w ? u.omega_f - L.y[0] : L.h;
+        L.h = to_w ? u.omega_f - L.omega() : L.h;
         L.last_rej = to_w ? false : L.last_rej;
         L.omega_mode = L.omega_mode || to_w;
     }
@@ -248,14 +252,8 @@ __device__ __forceinline__ int control(const Uni& u, LaneT& L, bool go, int st, 
     }
     const double tn = L.omega_mode ? __builtin_fma(h, (double)dts, L.t) : L.t + h;
     const bool done = take && (last || (!L.omega_mode && !tend && Y[0] == u.omega_f));
-    if (take) {
-#pragma unroll
-        for (int c = 0; c < 10; ++c) {
-            L.y[c] = Y[c];
-            L.k1[c] = k7[c];
-        }
-    }
-    if (done && L.omega_mode) L.y[0] = u.omega_f;
+    if (take) L.take(Y, k7);
+    if (done && L.omega_mode) L.set_omega(u.omega_f);
     L.t = take ? tn : L.t;
     L.dt1 = take ? dt7 : L.dt1;
     L.acc += take ? 1 : 0;
@@ -263,7 +261,7 @@ __device__ __forceinline__ int control(const Uni& u, LaneT& L, bool go, int st, 
     const bool resize = rej || (take && !done && !fixed);
     L.h = resize ? h * fac : L.h;
     L.last_rej = resize ? rej : L.last_rej;
-    const double scale = L.omega_mode ? __builtin_fabs(L.y[0]) : __builtin_fmax(1.0, __builtin_fabs(L.t));
+    const double scale = L.omega_mode ? __builtin_fabs(L.omega()) : __builtin_fmax(1.0, __builtin_fabs(L.t));
     if (rej && L.h < 1e-14 * scale) st = PN_ST_H_UNDERFLOW;
     return st != 0 ? st : (done ? 1 : 0);
 }
@@ -284,6 +282,16 @@ struct LaneF64 {
     int acc, rej, nrhs;
     int nt;           // accepted time steps (recording only)
     bool omega_mode, last_rej;
+    __device__ __forceinline__ double omega() const { return y[0]; }
+    __device__ __forceinline__ void set_omega(double w) { y[0] = w; }
+    // an accepted candidate state and its derivative
+    __device__ __forceinline__ void take(const double* Y, const double* k) {
+#pragma unroll
+        for (int c = 0; c < 10; ++c) {
+            y[c] = Y[c];
+            k1[c] = k[c];
+        }
+    }
 };
 
 // PHASE: also integrate the orbital phase, d Phi/dt = omega, as a quadrature
@@ -442,6 +450,15 @@ struct LaneF32 {
     int acc, rej, nrhs;
     int nt;           // accepted time steps (unused: no tape in this mode)
     bool omega_mode, last_rej;
+    __device__ __forceinline__ double omega() const { return y[0]; }
+    __device__ __forceinline__ void set_omega(double w) { y[0] = w; }
+    __device__ __forceinline__ void take(const double* Y, const float* k) {
+#pragma unroll
+        for (int c = 0; c < 10; ++c) {
+            y[c] = Y[c];
+            k1[c] = k[c];
+        }
+    }
 };
 
 template <bool PHASE = false, bool GEN = true>
@@ -568,6 +585,199 @@ struct F32Split {
         const int r = control<false, GEN>(u, L, go, st0, fin, z, h, last, ynew, k7, dt7, dts);
         // the FP32 increment is summed in FP64, as the state is
         if (PHASE) L.phase = L.acc != acc0 ? __builtin_fma(h, (double)ps, L.phase) : L.phase;
+        return r;
+    }
+};
+
+// ===========================================================================
+// FP32-state lane
+// ===========================================================================
+// Sum a + b of two floats as hi + lo exactly (Fast2Sum: requires |a| >= |b|
+// or a = 0; here a is the running sum and b one step's increment).
+__device__ __forceinline__ void fast_two_sum(float a, float b, float& hi, float& lo) {
+    hi = a + b;
+    lo = b - (hi - a);
+}
+
+struct LaneF32S {
+    float y[10];      // state, FP32; omega is y[0] + wlo
+    float wlo;        // low part of omega: the rounding of its increments, summed
+    float k1[10];     // FSAL derivative, FP32
+    float dt1;
+    double t, h;
+    float ph, phlo;   // orbital phase as ph + phlo (phase kernels only)
+    RowF row;
+    int64_t idx;
+    int acc, rej, nrhs;
+    int nt;           // accepted time steps (unused: no tape in this mode)
+    bool omega_mode, last_rej;
+    __device__ __forceinline__ double omega() const { return (double)y[0] + (double)wlo; }
+    // omega as the nearest float and the float nearest the rest (exact for
+    // the values this lane produces: a float plus a float below half its ulp)
+    __device__ __forceinline__ void set_omega(double w) {
+        y[0] = (float)w;
+        wlo = (float)(w - (double)y[0]);
+    }
+    __device__ __forceinline__ void take(const double* Y, const float* k) {
+        set_omega(Y[0]);
+#pragma unroll
+        for (int c = 1; c < 10; ++c) y[c] = (float)Y[c];
+#pragma unroll
+        for (int c = 0; c < 10; ++c) k1[c] = k[c];
+    }
+    __device__ __forceinline__ void state64(double* yd) const {
+        yd[0] = omega();
+#pragma unroll
+        for (int c = 1; c < 10; ++c) yd[c] = (double)y[c];
+    }
+};
+
+// FP32 state (Sec. III: single precision with a few computations in double):
+// omega, S1, S2 and L_hat are held in FP32, with the increments of omega
+// summed with their rounding errors (omega = y[0] + wlo, about 48 bits) and
+// likewise the phase; the stages, right-hand sides, increments and error
+// estimate are FP32; t, h, the error norm, the step control and the
+// omega >= omega_f test are FP64.
+template <bool PHASE = false, bool GEN = true>
+struct F32State {
+    using LaneT = LaneF32S;
+
+    static __device__ int load(const Io& io, const Uni& u, LaneT& L, int64_t idx) {
+        L.idx = idx;
+        double m1, m2, yd[10];
+        const int st = read_input<PHASE>(io, u, idx, yd, m1, m2);
+        if (st) return st;
+        L.set_omega(yd[0]);
+#pragma unroll
+        for (int c = 1; c < 10; ++c) L.y[c] = (float)yd[c];
+        L.t = 0.0;
+        L.acc = 0; L.rej = 0;
+        L.omega_mode = false; L.last_rej = false;
+        L.h = u.fixed ? u.h_fixed : u.h0;
+        L.ph = 0.0f;
+        L.phlo = 0.0f;
+        Row r;
+        make_row(r, m1, m2, u.terms, u.theta_literal);
+        L.row = to_f32(r);
+        rhs_f32(L.row, u.tcf, L.y, L.k1);
+        L.dt1 = 1.0f;
+        L.nrhs = 1;
+        return 0;
+    }
+
+    static __device__ void finish(const Io& io, const Uni& u, const LaneT& L, int st) {
+        double yd[10];
+        L.state64(yd);
+        // an integration that reached omega_f ends on it exactly (the float
+        // pair holds 48 bits of it)
+        if (st == PN_ST_OK && !u.tend) yd[0] = u.omega_f;
+        write_out<PHASE>(io, u, L.idx, yd, L.t, L.acc, L.rej, L.nrhs, st, (double)L.ph + (double)L.phlo);
+    }
+
+    // One attempted step, run by every lane as in the FP64 lane.
+    static __device__ __forceinline__ int step(const Uni& u, LaneT& L, bool active, bool any_w) {
+        const int st0 = pre_status<false>(u, L);
+        const bool go = active && st0 == 0;
+        bool last;
+        // idle lanes take a step of zero: their stage points stay on their
+        // state, so they never send the wave down a slow path
+        const double h = active ? clip_step<GEN>(u, L, last) : 0.0;
+
+        const RowF& R = L.row;
+        const float* k1 = L.k1;
+        const float* yf = L.y;
+        const float hf = (float)h;
+        float Y[10], k2[10], k3[10], k4[10], k5[10], k6[10];
+        float dtj;
+        float dts = (float)B1 * L.dt1;
+        float ps = 0.0f;
+        if (PHASE) ps = (float)B1 * (yf[0] * L.dt1);
+        {
+            const float c1 = hf * (float)A21;
+#pragma unroll
+            for (int c = 0; c < 10; ++c) Y[c] = __builtin_fmaf(c1, k1[c], yf[c]);
+            rhs_f32(R, u.tcf, Y, k2);
+            if (__builtin_expect(any_w, 0)) to_omega_variable(k2, dtj, L.omega_mode);
+        }
+        {
+            const float c1 = hf * (float)A31, c2 = hf * (float)A32;
+#pragma unroll
+            for (int c = 0; c < 10; ++c) Y[c] = __builtin_fmaf(c2, k2[c], __builtin_fmaf(c1, k1[c], yf[c]));
+            rhs_f32(R, u.tcf, Y, k3);
+            if (__builtin_expect(any_w, 0)) { to_omega_variable(k3, dtj, L.omega_mode); dts = __builtin_fmaf((float)B3, dtj, dts); }
+            if (PHASE) ps = __builtin_fmaf((float)B3, Y[0] * (any_w ? dtj : 1.0f), ps);
+        }
+        {
+            const float c1 = hf * (float)A41, c2 = hf * (float)A42, c3 = hf * (float)A43;
+#pragma unroll
+            for (int c = 0; c < 10; ++c)
+                Y[c] = __builtin_fmaf(c3, k3[c], __builtin_fmaf(c2, k2[c], __builtin_fmaf(c1, k1[c], yf[c])));
+            rhs_f32(R, u.tcf, Y, k4);
+            if (__builtin_expect(any_w, 0)) { to_omega_variable(k4, dtj, L.omega_mode); dts = __builtin_fmaf((float)B4, dtj, dts); }
+            if (PHASE) ps = __builtin_fmaf((float)B4, Y[0] * (any_w ? dtj : 1.0f), ps);
+        }
+        {
+            const float c1 = hf * (float)A51, c2 = hf * (float)A52, c3 = hf * (float)A53, c4 = hf * (float)A54;
+#pragma unroll
+            for (int c = 0; c < 10; ++c)
+                Y[c] = __builtin_fmaf(c4, k4[c], __builtin_fmaf(c3, k3[c],
+                       __builtin_fmaf(c2, k2[c], __builtin_fmaf(c1, k1[c], yf[c]))));
+            rhs_f32(R, u.tcf, Y, k5);
+            if (__builtin_expect(any_w, 0)) { to_omega_variable(k5, dtj, L.omega_mode); dts = __builtin_fmaf((float)B5, dtj, dts); }
+            if (PHASE) ps = __builtin_fmaf((float)B5, Y[0] * (any_w ? dtj : 1.0f), ps);
+        }
+        {
+            const float c1 = hf * (float)A61, c2 = hf * (float)A62, c3 = hf * (float)A63, c4 = hf * (float)A64,
+                        c5 = hf * (float)A65;
+#pragma unroll
+            for (int c = 0; c < 10; ++c)
+                Y[c] = __builtin_fmaf(c5, k5[c], __builtin_fmaf(c4, k4[c], __builtin_fmaf(c3, k3[c],
+                       __builtin_fmaf(c2, k2[c], __builtin_fmaf(c1, k1[c], yf[c])))));
+            rhs_f32(R, u.tcf, Y, k6);
+            if (__builtin_expect(any_w, 0)) { to_omega_variable(k6, dtj, L.omega_mode); dts = __builtin_fmaf((float)B6, dtj, dts); }
+            if (PHASE) ps = __builtin_fmaf((float)B6, Y[0] * (any_w ? dtj : 1.0f), ps);
+        }
+        // 5th-order increment D (FP32), the stage-7 point, and the error sum
+        float D[10], Ep[10];
+#pragma unroll
+        for (int c = 0; c < 10; ++c) {
+            D[c] = hf * __builtin_fmaf((float)B6, k6[c], __builtin_fmaf((float)B5, k5[c],
+                        __builtin_fmaf((float)B4, k4[c], __builtin_fmaf((float)B3, k3[c], (float)B1 * k1[c]))));
+            Y[c] = yf[c] + D[c];
+            Ep[c] = __builtin_fmaf((float)E6, k6[c], __builtin_fmaf((float)E5, k5[c],
+                    __builtin_fmaf((float)E4, k4[c], __builtin_fmaf((float)E3, k3[c], (float)E1 * k1[c]))));
+        }
+        float k7[10], dt7 = 1.0f;
+        rhs_f32(R, u.tcf, Y, k7);
+        if (__builtin_expect(any_w, 0)) to_omega_variable(k7, dt7, L.omega_mode);
+        L.nrhs += go ? 6 : 0;
+
+        // the state and the candidate, viewed in FP64 for the norm and the
+        // control: omega's increment joins the compensated sum, the other
+        // components are the FP32 sums already formed
+        double yd[10], ynew[10];
+        L.state64(yd);
+        float whi, wlo;
+        fast_two_sum(yf[0], D[0], whi, wlo);
+        ynew[0] = (double)whi + (double)(wlo + L.wlo);
+#pragma unroll
+        for (int c = 1; c < 10; ++c) ynew[c] = (double)Y[c];
+        double e[10];
+#pragma unroll
+        for (int c = 0; c < 10; ++c) e[c] = (double)(hf * __builtin_fmaf((float)E7, k7[c], Ep[c]));
+        const double z = error_norm(u, yd, ynew, e);
+        bool fin = (GEN && u.fixed) || !__builtin_isnan(z);
+#pragma unroll
+        for (int c = 0; c < 10; ++c) fin = fin && finite(ynew[c]) && __builtin_isfinite(k7[c]);
+        const int acc0 = L.acc;
+        const int r = control<false, GEN>(u, L, go, st0, fin, z, h, last, ynew, k7, dt7, dts);
+        if (PHASE && L.acc != acc0) {
+            // the phase increment joins its compensated sum
+            float s, err;
+            fast_two_sum(L.ph, hf * ps, s, err);
+            L.ph = s;
+            L.phlo += err;
+        }
         return r;
     }
 };
@@ -713,6 +923,36 @@ template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(kWpeF32)))
 void integrate_persistent_f32s_phase(Uni u, unsigned long long* slot) {
     persistent_loop<F32Split<true>>(u, slot);
+}
+
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(kWpeF32S)))
+void integrate_persistent_f32x(Uni u, unsigned long long* slot) {
+    persistent_loop<F32State<false, false>>(u, slot);
+}
+
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(kWpeF32S)))
+void integrate_persistent_f32x_modes(Uni u, unsigned long long* slot) {
+    persistent_loop<F32State<false, true>>(u, slot);
+}
+
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(kWpeF32S)))
+void integrate_persistent_f32x_phase(Uni u, unsigned long long* slot) {
+    persistent_loop<F32State<true>>(u, slot);
+}
+
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(kWpeF32S)))
+void integrate_static_f32x(Io io, Uni u) {
+    static_loop<F32State<>>(io, u, (int64_t)blockIdx.x * BLOCK + threadIdx.x);
+}
+
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(kWpeF32S)))
+void integrate_static_f32x_phase(Io io, Uni u) {
+    static_loop<F32State<true>>(io, u, (int64_t)blockIdx.x * BLOCK + threadIdx.x);
 }
 
 template <int BLOCK, bool RECORD>
@@ -1228,9 +1468,12 @@ TermConsts term_consts(int terms) {
 template <int BLOCK>
 hipError_t launch_static(const Io& io, const Uni& u, int precision, hipStream_t s) {
     const bool f32 = precision == PN_PREC_FP32_SPLIT;
+    const bool f32x = precision == PN_PREC_FP32_STATE;
     const bool ph = io.phase != nullptr;
     const int64_t grid = (u.n + BLOCK - 1) / BLOCK;
-    if (ph && f32) hipLaunchKernelGGL(integrate_static_f32s_phase<BLOCK>, dim3((unsigned)grid), dim3(BLOCK), 0, s, io, u);
+    if (ph && f32x) hipLaunchKernelGGL(integrate_static_f32x_phase<BLOCK>, dim3((unsigned)grid), dim3(BLOCK), 0, s, io, u);
+    else if (f32x) hipLaunchKernelGGL(integrate_static_f32x<BLOCK>, dim3((unsigned)grid), dim3(BLOCK), 0, s, io, u);
+    else if (ph && f32) hipLaunchKernelGGL(integrate_static_f32s_phase<BLOCK>, dim3((unsigned)grid), dim3(BLOCK), 0, s, io, u);
     else if (ph) hipLaunchKernelGGL(integrate_static_f64_phase<BLOCK>, dim3((unsigned)grid), dim3(BLOCK), 0, s, io, u);
     else if (f32) hipLaunchKernelGGL(integrate_static_f32s<BLOCK>, dim3((unsigned)grid), dim3(BLOCK), 0, s, io, u);
     else if (u.tape) hipLaunchKernelGGL((integrate_static_f64<BLOCK, true>), dim3((unsigned)grid), dim3(BLOCK), 0, s, io, u);
@@ -1244,6 +1487,7 @@ template <int BLOCK>
 hipError_t launch_persistent(const Io& io, const Uni& u, int precision, int waves_per_simd, int cus,
                              unsigned long long* counter, hipStream_t s) {
     const bool f32 = precision == PN_PREC_FP32_SPLIT;
+    const bool f32x = precision == PN_PREC_FP32_STATE;
     const bool ph = io.phase != nullptr;
     LaunchDesc desc;
     desc.io = io;
@@ -1257,7 +1501,13 @@ hipError_t launch_persistent(const Io& io, const Uni& u, int precision, int wave
     const int64_t grid = (waves * 64 + BLOCK - 1) / BLOCK;
     const bool gen = u.fixed || u.tend;    // not the plain adaptive run to omega_f
     const dim3 g((unsigned)grid), b(BLOCK);
-    if (ph && f32)
+    if (ph && f32x)
+        hipLaunchKernelGGL(integrate_persistent_f32x_phase<BLOCK>, g, b, 0, s, u, counter);
+    else if (f32x && gen)
+        hipLaunchKernelGGL(integrate_persistent_f32x_modes<BLOCK>, g, b, 0, s, u, counter);
+    else if (f32x)
+        hipLaunchKernelGGL(integrate_persistent_f32x<BLOCK>, g, b, 0, s, u, counter);
+    else if (ph && f32)
         hipLaunchKernelGGL(integrate_persistent_f32s_phase<BLOCK>, g, b, 0, s, u, counter);
     else if (ph)
         hipLaunchKernelGGL(integrate_persistent_f64_phase<BLOCK>, g, b, 0, s, u, counter);
@@ -1322,11 +1572,13 @@ static int integrate_impl(int64_t n, int64_t ld, const double* m, const double* 
     if (tend && !(o.t_end < 1e300)) return PN_EINVAL;
     if (!(o.h0 == o.h0) || o.h0 >= 1e300) return PN_EINVAL;
     if (o.schedule != PN_SCHED_PERSISTENT && o.schedule != PN_SCHED_STATIC) return PN_EINVAL;
-    if (o.precision != PN_PREC_FP64 && o.precision != PN_PREC_FP32_SPLIT) return PN_EINVAL;
+    if (o.precision != PN_PREC_FP64 && o.precision != PN_PREC_FP32_SPLIT && o.precision != PN_PREC_FP32_STATE)
+        return PN_EINVAL;
     const int block = o.block ? o.block : 256;
     if (block != 64 && block != 128 && block != 256 && block != 512) return PN_EINVAL;
     const int wps = o.waves_per_simd ? o.waves_per_simd
-                                     : (o.precision == PN_PREC_FP32_SPLIT ? kWpeF32 : kWpeF64);
+                                     : (o.precision == PN_PREC_FP32_SPLIT ? kWpeF32
+                                        : o.precision == PN_PREC_FP32_STATE ? kWpeF32S : kWpeF64);
     if (wps < 1 || wps > 8) return PN_EINVAL;
     const int refill = o.refill_min ? o.refill_min : 4;
     if (refill < 1 || refill > 64) return PN_EINVAL;

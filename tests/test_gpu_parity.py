@@ -115,15 +115,18 @@ def test_observables_parity():
 @pytest.mark.parametrize("workload,h", [("equal_mass_maxspin_1k", 40.0), ("adjoint_64k", 50.0),
                                         ("q1to4_1M", 100.0), ("batching_4M", 100.0)])
 def test_fixed_step_parity(workload, h):
-    """1e-12 normwise relative, or 1e-15 per step for runs longer than 1000
-    steps (the batching workload takes up to ~35,000 fixed steps, over which
-    independent roundings accumulate past 1e-12)."""
+    """1e-12 normwise relative.  The batching workload's runs of more than
+    1000 fixed steps (up to ~35,000) accumulate independent roundings past
+    that: for them the bar is the measured growth, at most 6.5e-16 per step
+    (and 1.0e-13 per square root of the step count), rounded up to 1e-15 per
+    step; its runs of up to 1000 steps keep 1e-12 (measured 5.9e-13)."""
     pop = P.generate(workload, 777)          # several waves and a ragged tail
     ro = run_oracle(pop, h_fixed=h)
     rg = run_gpu(pop, h_fixed=h)
     assert (rg["status"] == ro["status"]).all()
     np.testing.assert_array_equal(rg["steps"][:2], ro["steps"][:2])
-    bound = np.maximum(1e-12, 1e-15 * ro["steps"][0])
+    long_run = (ro["steps"][0] > 1000) if workload == "batching_4M" else np.zeros(pop["n"], bool)
+    bound = np.where(long_run, 1e-15 * ro["steps"][0], 1e-12)
     err = normwise_rel(rg["y"], ro["y"], pop["S"])
     terr = np.abs(rg["t"] / ro["t"] - 1)
     steps = ro["steps"][0]
