@@ -75,7 +75,7 @@ def test_invalid_arguments_return_einval_without_a_device(lib):
     assert call(10, 10, opt=bad) == PN_EINVAL
     bad = PnOpts(); bad.terms = 64
     assert call(10, 10, opt=bad) == PN_EINVAL
-    bad = PnOpts(); bad.precision = 2
+    bad = PnOpts(); bad.precision = 3
     assert call(10, 10, opt=bad) == PN_EINVAL
     assert call(0, 0) == PN_OK                       # empty batch: nothing to do
     ph = lambda n, ld, out, tol=1e-8: lib.pn_integrate_phase(
