@@ -339,6 +339,29 @@ def leg_fp32split(api, pop, d, ref64: dict, stream, reps: int = 5, precision: st
                          "cpu_baseline.crosscheck)"}
 
 
+def leg_check(api, pop, d, stream, fractions=(0.001, 0.01)) -> dict:
+    """The CPU check of Sec. III as the library runs it (integrate_checked):
+    a random fraction of the population integrated on the host threads while
+    the GPU integrates all of it, then compared at the 1e-8 parity bar.  Wall
+    time of the checked call against the GPU integration alone."""
+    import torch
+    cores = len(os.sched_getaffinity(0))
+    res = {"workload": pop["workload"], "n": pop["n"], "host_threads": cores, "runs": []}
+    for f in fractions:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, rep = api.integrate_checked(d["m"], d["S"], d["L"], d["omega0"], pop["omega_f"], pop["tol"],
+                                       fraction=f, seed=11, host_inputs=pop, nthreads=cores, stream=stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        res["runs"].append({"fraction": f, "checked": rep["checked"], "wall_ms": wall * 1e3,
+                            "host_ms": rep["host_seconds"] * 1e3, "flagged": rep["flagged"],
+                            "status_mismatches": rep["status_mismatches"],
+                            "step_mismatches": rep["step_mismatches"], "max_dot_diff": rep["max_dot_diff"],
+                            "ok": rep["ok"]})
+    return res
+
+
 def leg_batching(api, population, stream, reps: int = 3, n: int | None = None) -> dict:
     """The batching workload (4,194,304 inspirals, omega0 log-uniform in
     [0.002, 0.01], q in [1, 10]): the persistent refill kernel against one
@@ -709,6 +732,7 @@ def main() -> int:
         res["fp32split"] = leg_fp32split(api, pop, d, ref64, stream)
         res["fp32_state"] = leg_fp32split(api, pop, d, ref64, stream, precision="fp32")
         res["batching"] = leg_batching(api, population, stream)
+        res["cpu_check"] = leg_check(api, pop, d, stream)
     if not args.no_cpu_baseline:
         gpu = {"dots": out["dots"].cpu().numpy(), "steps": steps, "status": status}
         # FP32-split is checked against the FP64 oracle with its own error bound

@@ -198,6 +198,54 @@ int pn_cost_order(int64_t n, int64_t ld, const double* m, const double* S0, cons
                   size_t ws_bytes, void* stream);
 
 /*
+ * The check of GPU results against the CPU on a subset (Sec. III: kernel
+ * failures on the GPU go unreported, so the paper integrated part of each
+ * population on the CPU as well and compared).  A host integrator of the
+ * same method (Eqs. (1)-(4), adaptive Dormand-Prince with the same error
+ * norm, step control and final stretch in omega, plain FP64 with the C
+ * library's cube root and log) runs on host threads while the GPU works;
+ * its final states agree with the FP64 kernels' to rounding.
+ *
+ * pn_check_integrate_host -- the host integrator itself, synchronously:
+ *   arguments, layout and outputs as pn_integrate but in HOST memory (no
+ *   dots); pn_opts.precision, schedule, block, waves_per_simd, refill_min
+ *   and order are ignored (it always integrates in FP64).  nthreads <= 0:
+ *   one thread per core this process may run on.
+ * pn_check_start -- copies k sampled inspirals (host SoA arrays with leading
+ *   dimension ld: m [2][ld], S0 [6][ld], L0 [3][ld], omega0 [ld]) and starts
+ *   integrating them on nthreads host threads (<= 0: one per core this
+ *   process may run on); returns at once with *handle set.  PN_EINVAL for
+ *   bad sizes, pointers or options; PN_ENOMEM if no thread could be started.
+ * pn_check_finish -- waits for those threads and compares: GPU outputs of the
+ *   same k inspirals in the same order (host copies: y [10][ld_gpu],
+ *   steps [3][ld_gpu], status [ld_gpu]).  An inspiral is flagged when its
+ *   status differs (flag bit 1) or when, both being PN_ST_OK, one of its unit
+ *   dot products S1h.S2h, S1h.Lh, S2h.Lh differs by more than dot_tol (bit 2;
+ *   1e-8 is the FP64 parity bar, FP32 modes need about 1e-3).  Differing step
+ *   counts are counted, not flagged.  flags: optional int32 [k] output;
+ *   report: optional.  Frees the handle (also on PN_EINVAL).
+ */
+typedef struct pn_check pn_check;
+typedef struct pn_check_report {
+    int64_t checked;            /* inspirals integrated on the host */
+    int64_t status_mismatches;
+    int64_t step_mismatches;    /* accepted or rejected step counts differ */
+    int64_t flagged;            /* inspirals with a status or dot-product disagreement */
+    double  max_dot_diff;       /* largest |GPU - host| over the dot products (both OK) */
+    double  host_seconds;       /* wall time of the host integration */
+} pn_check_report;
+int pn_check_integrate_host(int64_t n, int64_t ld, const double* m, const double* S0, const double* L0,
+                            const double* omega0, double omega_f, double tol, const pn_opts* opt,
+                            double* y_final, double* t_final, int32_t* steps, int32_t* status,
+                            int32_t nthreads);
+int pn_check_start(pn_check** handle, int64_t k, int64_t ld, const double* m, const double* S0,
+                   const double* L0, const double* omega0, double omega_f, double tol,
+                   const pn_opts* opt, int32_t nthreads);
+int pn_check_finish(pn_check* handle, const double* y_gpu, const int32_t* steps_gpu,
+                    const int32_t* status_gpu, int64_t ld_gpu, double dot_tol, int32_t* flags,
+                    pn_check_report* report);
+
+/*
  * pn_integrate_noalloc -- pn_integrate for callers that cannot allocate
  * device memory: code being captured into a HIP graph, tight serving loops,
  * harnesses that forbid hipMalloc.  Same arguments, kernels, outputs and

@@ -28,7 +28,8 @@ EXPORTS = ("pn_integrate", "pn_rhs", "pn_observables", "pn_strerror", "pn_versio
            "pn_tape_stride", "pn_integrate_record", "pn_adjoint_workspace_bytes",
            "pn_integrate_adjoint", "pn_histogram", "pn_histogram2d", "pn_pearson", "pn_kde",
            "pn_ks_workspace_bytes", "pn_ks_uniform", "pn_stats_workspace_bytes", "pn_generate",
-           "pn_autotune", "pn_integrate_phase", "pn_fma_rate", "pn_shutdown", "pn_integrate_noalloc", "pn_cost_order", "pn_cost_order_workspace_bytes")
+           "pn_autotune", "pn_integrate_phase", "pn_fma_rate", "pn_shutdown", "pn_integrate_noalloc", "pn_cost_order", "pn_cost_order_workspace_bytes",
+           "pn_check_integrate_host", "pn_check_start", "pn_check_finish")
 
 
 class PnOpts(C.Structure):
@@ -52,6 +53,11 @@ class PnGenSpec(C.Structure):
     _fields_ = [("q_lo", C.c_double), ("q_hi", C.c_double), ("chi1_lo", C.c_double), ("chi1_hi", C.c_double),
                 ("chi2_lo", C.c_double), ("chi2_hi", C.c_double), ("omega0_lo", C.c_double),
                 ("omega0_hi", C.c_double), ("seed", C.c_uint64)]
+
+
+class PnCheckReport(C.Structure):
+    _fields_ = [("checked", C.c_int64), ("status_mismatches", C.c_int64), ("step_mismatches", C.c_int64),
+                ("flagged", C.c_int64), ("max_dot_diff", C.c_double), ("host_seconds", C.c_double)]
 
 
 class PnError(RuntimeError):
@@ -78,6 +84,12 @@ def load():
     L.pn_cost_order_workspace_bytes.restype = C.c_size_t
     L.pn_cost_order.argtypes = [i64, i64, vp, vp, vp, vp, dbl, vp, vp, C.c_size_t, vp]
     L.pn_cost_order.restype = C.c_int
+    L.pn_check_integrate_host.argtypes = [i64, i64, vp, vp, vp, vp, dbl, dbl, popts, vp, vp, vp, vp, C.c_int32]
+    L.pn_check_integrate_host.restype = C.c_int
+    L.pn_check_start.argtypes = [C.POINTER(vp), i64, i64, vp, vp, vp, vp, dbl, dbl, popts, C.c_int32]
+    L.pn_check_start.restype = C.c_int
+    L.pn_check_finish.argtypes = [vp, vp, vp, vp, i64, dbl, vp, C.POINTER(PnCheckReport)]
+    L.pn_check_finish.restype = C.c_int
     L.pn_integrate_noalloc.argtypes = [i64, i64, vp, vp, vp, vp, dbl, dbl, popts, vp, vp, vp, vp, vp, vp]
     L.pn_integrate_noalloc.restype = C.c_int
     L.pn_integrate_phase.argtypes = [i64, i64, vp, vp, vp, vp, dbl, dbl, popts, vp, vp, vp, vp, vp, vp, vp]

@@ -10,6 +10,8 @@ from __future__ import annotations
 
 import ctypes as C
 
+import numpy as np
+
 import torch
 
 from . import _lib
@@ -126,6 +128,82 @@ def pn_integrate(m, S0, L0, omega0, omega_f, tol, opts: PnOpts | None = None, ou
     dots [3, n] or None).  Asynchronous on the current stream.
     """
     return _integrate("plain", m, S0, L0, omega0, omega_f, tol, opts, out, dots, stream)
+
+
+def _host_soa(a, comps, n, name):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if a.shape != ((comps, n) if comps > 1 else (n,)):
+        raise ValueError(f"{name}: expected shape {(comps, n) if comps > 1 else (n,)}, got {a.shape}")
+    return a
+
+
+def check_integrate_host(m, S0, L0, omega0, omega_f, tol, opts: PnOpts | None = None, nthreads: int = 0) -> dict:
+    """The host integrator of the CPU check (pn_check_integrate_host) on
+    numpy arrays: dict(y [10, n], t [n], steps [3, n], status [n])."""
+    omega0 = np.ascontiguousarray(omega0, dtype=np.float64)
+    n = omega0.shape[0]
+    m, S0, L0 = _host_soa(m, 2, n, "m"), _host_soa(S0, 6, n, "S0"), _host_soa(L0, 3, n, "L0")
+    y = np.empty((10, n)); t = np.empty(n)
+    steps = np.empty((3, n), dtype=np.int32); status = np.empty(n, dtype=np.int32)
+    o = opts if opts is not None else make_opts()
+    p = lambda a: a.ctypes.data_as(C.c_void_p)
+    rc = load().pn_check_integrate_host(n, n, p(m), p(S0), p(L0), p(omega0), float(omega_f), float(tol),
+                                        C.byref(o), p(y), p(t), p(steps), p(status), int(nthreads))
+    check(rc, "pn_check_integrate_host")
+    return {"y": y, "t": t, "steps": steps, "status": status}
+
+
+def integrate_checked(m, S0, L0, omega0, omega_f, tol, opts: PnOpts | None = None, out=None,
+                      fraction: float = 0.01, sample=None, seed: int = 0, dot_tol: float | None = None,
+                      nthreads: int = 0, host_inputs: dict | None = None, stream=None):
+    """pn_integrate with the CPU check of Sec. III running alongside: a
+    random `fraction` of the inspirals (or the indices in `sample`) is
+    integrated on host threads (pn_check_start) while the GPU integrates all
+    of them, then the GPU's outputs for the sample are compared
+    (pn_check_finish).  dot_tol: 1e-8 for FP64, 1e-3 for the FP32 modes
+    unless given.  host_inputs: optional numpy copies of the inputs (dict
+    m, S, L, omega0), saving the device-to-host copy of the sample.
+    Returns (outputs, report dict with the sample indices and their flags)."""
+    n = int(omega0.shape[0])
+    o = opts if opts is not None else make_opts()
+    if sample is None:
+        k = max(1, int(round(n * fraction))) if n > 0 else 0
+        sample = np.sort(np.random.default_rng(seed).choice(n, size=k, replace=False)) if k else np.zeros(0, np.int64)
+    sample = np.asarray(sample, dtype=np.int64)
+    k = sample.size
+    if k and (sample.min() < 0 or sample.max() >= n):
+        raise ValueError("sample indices must lie in [0, n)")
+    if host_inputs is not None:
+        hm = np.ascontiguousarray(host_inputs["m"][:, sample]); hS = np.ascontiguousarray(host_inputs["S"][:, sample])
+        hL = np.ascontiguousarray(host_inputs["L"][:, sample]); hw = np.ascontiguousarray(host_inputs["omega0"][sample])
+    else:
+        idx = torch.from_numpy(sample).to(omega0.device)
+        hm = m[:, idx].cpu().numpy(); hS = S0[:, idx].cpu().numpy()
+        hL = L0[:, idx].cpu().numpy(); hw = omega0[idx].cpu().numpy()
+    hm, hS, hL, hw = (np.ascontiguousarray(a, dtype=np.float64) for a in (hm, hS, hL, hw))
+    handle = C.c_void_p()
+    p = lambda a: a.ctypes.data_as(C.c_void_p)
+    rc = load().pn_check_start(C.byref(handle), k, k, p(hm), p(hS), p(hL), p(hw), float(omega_f), float(tol),
+                               C.byref(o), int(nthreads))
+    check(rc, "pn_check_start")
+    try:
+        out = pn_integrate(m, S0, L0, omega0, omega_f, tol, o, out=out, stream=stream)
+        idx = torch.from_numpy(sample).to(omega0.device)
+        gy = np.ascontiguousarray(out["y"][:, idx].cpu().numpy())
+        gs = np.ascontiguousarray(out["steps"][:, idx].cpu().numpy())
+        gst = np.ascontiguousarray(out["status"][idx].cpu().numpy())
+    except BaseException:
+        load().pn_check_finish(handle, None, None, None, 0, 0.0, None, None)
+        raise
+    if dot_tol is None:
+        dot_tol = 1e-8 if o.precision == _lib.PN_PREC_FP64 else 1e-3
+    flags = np.zeros(k, dtype=np.int32)
+    rep = _lib.PnCheckReport()
+    rc = load().pn_check_finish(handle, p(gy), p(gs), p(gst), k, float(dot_tol), p(flags), C.byref(rep))
+    check(rc, "pn_check_finish")
+    report = {f: getattr(rep, f) for f, _ in _lib.PnCheckReport._fields_}
+    report.update({"dot_tol": dot_tol, "sample": sample, "flags": flags, "ok": rep.flagged == 0})
+    return out, report
 
 
 def pn_integrate_noalloc(m, S0, L0, omega0, omega_f, tol, out: dict, opts: PnOpts | None = None,

@@ -23,7 +23,7 @@ RESOURCE_REPORT = os.path.join(HERE, "build_resource_usage.txt")
 
 SOURCES = [os.path.join(CSRC, "pn_lib.hip"), os.path.join(CSRC, "pn_stats.hip"),
            os.path.join(CSRC, "pn_generate.hip"), os.path.join(CSRC, "pn_probe.hip"),
-           os.path.join(CSRC, "pn_order.hip")]
+           os.path.join(CSRC, "pn_order.hip"), os.path.join(CSRC, "pn_check.cpp")]
 
 
 def hipcc() -> str:
