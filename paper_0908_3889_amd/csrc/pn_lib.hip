@@ -30,11 +30,8 @@ namespace pn {
 // Occupancy targets (waves per SIMD) the integration kernels are compiled
 // for; chosen by measurement (register budget 512/target per lane).
 constexpr int kWpeF64 = 2;
-constexpr int kWpeF32 = 3;
-#ifndef PN_WPE_F32S
-#define PN_WPE_F32S 3
-#endif
-constexpr int kWpeF32S = PN_WPE_F32S;
+constexpr int kWpeF32 = 3;     // FP32-split
+constexpr int kWpeF32S = 3;    // FP32-state (4 spills 23 VGPRs and is slower)
 
 // ---------------------------------------------------------------------------
 // Dormand-Prince RK5(4)7M tableau (Dormand & Prince 1980)
