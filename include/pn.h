@@ -399,6 +399,35 @@ int pn_integrate_adjoint(int64_t n, int64_t ld, const double* m, double omega_f,
                          double* workspace, size_t ws_bytes, const int32_t* order, void* stream);
 
 /*
+ * pn_ckpt_bytes -- bytes of the tape of n inspirals recorded with cap_steps
+ * and ckpt_every (n * pn_tape_stride(cap_steps, ckpt_every) doubles); 0 for
+ * sizes the record call refuses.
+ */
+size_t pn_ckpt_bytes(int64_t n, int64_t cap_steps, int32_t ckpt_every);
+
+/*
+ * pn_integrate_replay -- the recorded integration's map with its step sizes
+ * frozen, evaluated at any initial state: from (m, S0, L0, omega0) it takes
+ * the n_t time steps h_0 .. h_{n_t-1} of the tape, then its n_w omega-steps,
+ * the last of size omega_f - omega, and ends on omega_f (the Dormand-Prince
+ * steps of Sec. II without error control; the map that pn_integrate_adjoint
+ * differentiates).  Central differences of this map check the adjoint with
+ * the steps held fixed.  tape, cap_steps, ckpt_every: as recorded by
+ * pn_integrate_record (only the counts and step sizes are read).  status:
+ * the recorded run's statuses, or NULL when every inspiral ended PN_ST_OK;
+ * DONE_AT_START keeps the initial state (t = 0), any other failure gives NaN.
+ * Outputs y_final [10][ld], t_final [ld] (device).  A row that does not hold
+ * the counts of a recorded run, or inputs that pn_integrate refuses, give
+ * NaN outputs.  opt: terms and theta_literal as recorded; precision FP64, no
+ * t_end, no h_fixed (else PN_EINVAL).
+ */
+int pn_integrate_replay(int64_t n, int64_t ld, const double* m, const double* S0, const double* L0,
+                        const double* omega0, double omega_f, const pn_opts* opt, const double* tape,
+                        int64_t cap_steps, int32_t ckpt_every, const int32_t* status, double* y_final,
+                        double* t_final,
+                        void* stream);
+
+/*
  * The statistics of Sec. V over per-inspiral values, e.g. the dot products
  * that pn_integrate writes to `dots` (final) and pn_observables gives for the
  * initial state.  All arrays are device float64 SoA with leading dimension

@@ -325,6 +325,28 @@ def pn_integrate_record(m, S0, L0, omega0, omega_f, tol, opts: PnOpts | None = N
     return out
 
 
+def pn_ckpt_bytes(n: int, cap_steps: int, ckpt_every: int) -> int:
+    return int(load().pn_ckpt_bytes(int(n), int(cap_steps), int(ckpt_every)))
+
+
+def pn_integrate_replay(m, S0, L0, omega0, omega_f, rec: dict, opts: PnOpts | None = None, stream=None) -> dict:
+    """The recorded run's map with its step sizes frozen (rec: the dict of
+    pn_integrate_record), evaluated at the initial state (m, S0, L0, omega0)
+    (contiguous inputs).  Returns {'y': [10, n], 't': [n]}."""
+    n = _check_inputs(m, S0, L0, omega0)
+    if n != int(rec["tape"].shape[0]):
+        raise ValueError("the tape must hold one row per inspiral")
+    out = {"y": torch.empty((10, n), dtype=torch.float64, device=omega0.device),
+           "t": torch.empty((n,), dtype=torch.float64, device=omega0.device)}
+    o = opts if opts is not None else make_opts()
+    p = lambda t: C.c_void_p(t.data_ptr())
+    rc = load().pn_integrate_replay(n, n, p(m), p(S0), p(L0), p(omega0), float(omega_f), C.byref(o),
+                                    p(rec["tape"]), rec["cap_steps"], rec["ckpt_every"], p(rec["status"]),
+                                    p(out["y"]), p(out["t"]), _stream(stream))
+    check(rc, "pn_integrate_replay")
+    return out
+
+
 def pn_integrate_adjoint(m, omega_f, rec: dict, gy, gt=None, opts: PnOpts | None = None,
                          order=None, stream=None) -> dict:
     """Gradients of sum(gy * y_final) + sum(gt * t_final) with respect to

@@ -1303,6 +1303,117 @@ __global__ __launch_bounds__(BLOCK) void adjoint_kernel(AdjIo io, AdjUni u) {
     adjoint_one(io, u, idx, io.ws + j, ys, nx);
 }
 
+// ---------------------------------------------------------------------------
+// Replay of a recorded step sequence (no error control): the map whose
+// discrete adjoint pn_integrate_adjoint computes, evaluated at any initial
+// state.  One inspiral per lane.
+// ---------------------------------------------------------------------------
+struct ReplayIo {
+    const double* __restrict__ m;
+    const double* __restrict__ S0;
+    const double* __restrict__ L0;
+    const double* __restrict__ w0;
+    const int32_t* __restrict__ status; // [ld] of the recorded run, or null (all OK)
+    double* __restrict__ y;             // [10][ld]
+    double* __restrict__ t;             // [ld]
+};
+
+// the stage derivative as stage_deriv, and the rate of t along the variable
+// of the step (1 in a time step, dt/domega = 1/f_0 in an omega-step)
+__device__ __forceinline__ double stage_deriv_t(const Row& R, const TermConsts& tc, const LogBase& lb,
+                                                const double* Y, double* k, bool om) {
+    rhs<Row, true>(R, tc, lb, Y, k);
+    if (!om) return 1.0;
+    const double s = 1.0 / k[0];
+#pragma unroll
+    for (int c = 1; c < 10; ++c) k[c] *= s;
+    k[0] = 1.0;
+    return s;
+}
+
+// one replayed step with t: y <- y + h sum b_i k_i, t <- t + h sum b_i r_i
+__device__ __forceinline__ void replay_step_t(const Row& R, const TermConsts& tc, double* y, double& t, double h,
+                                              bool om) {
+    double k1[10], k2[10], k3[10], k4[10], k5[10], k6[10], Y[10];
+    const LogBase lb = log_base(R, y);
+    const double r1 = stage_deriv_t(R, tc, lb, y, k1, om);
+#pragma unroll
+    for (int c = 0; c < 10; ++c) Y[c] = __builtin_fma(h * A21, k1[c], y[c]);
+    stage_deriv_t(R, tc, lb, Y, k2, om);
+#pragma unroll
+    for (int c = 0; c < 10; ++c) Y[c] = __builtin_fma(h * A32, k2[c], __builtin_fma(h * A31, k1[c], y[c]));
+    const double r3 = stage_deriv_t(R, tc, lb, Y, k3, om);
+#pragma unroll
+    for (int c = 0; c < 10; ++c)
+        Y[c] = __builtin_fma(h * A43, k3[c], __builtin_fma(h * A42, k2[c], __builtin_fma(h * A41, k1[c], y[c])));
+    const double r4 = stage_deriv_t(R, tc, lb, Y, k4, om);
+#pragma unroll
+    for (int c = 0; c < 10; ++c)
+        Y[c] = __builtin_fma(h * A54, k4[c], __builtin_fma(h * A53, k3[c],
+               __builtin_fma(h * A52, k2[c], __builtin_fma(h * A51, k1[c], y[c]))));
+    const double r5 = stage_deriv_t(R, tc, lb, Y, k5, om);
+#pragma unroll
+    for (int c = 0; c < 10; ++c)
+        Y[c] = __builtin_fma(h * A65, k5[c], __builtin_fma(h * A64, k4[c], __builtin_fma(h * A63, k3[c],
+               __builtin_fma(h * A62, k2[c], __builtin_fma(h * A61, k1[c], y[c])))));
+    const double r6 = stage_deriv_t(R, tc, lb, Y, k6, om);
+#pragma unroll
+    for (int c = 0; c < 10; ++c)
+        y[c] = __builtin_fma(h * B6, k6[c], __builtin_fma(h * B5, k5[c], __builtin_fma(h * B4, k4[c],
+               __builtin_fma(h * B3, k3[c], __builtin_fma(h * B1, k1[c], y[c])))));
+    t = __builtin_fma(h, B1 * r1 + B3 * r3 + B4 * r4 + B5 * r5 + B6 * r6, t);
+}
+
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void replay_kernel(ReplayIo io, AdjUni u) {
+    const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (i >= u.n) return;
+    const int64_t ld = u.ld;
+    const double* tp = u.tape + i * u.tape_stride;
+    const double m1 = io.m[i], m2 = io.m[ld + i];
+    double y[10];
+    y[0] = io.w0[i];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) y[1 + c] = io.S0[c * ld + i];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) y[7 + c] = io.L0[c * ld + i];
+    double t = 0.0;
+    // a recorded run that ended at once keeps its initial state; any other
+    // recorded failure, a row that does not hold the counts of a recorded
+    // run (non-integer, negative, or more steps than the tape holds), or
+    // inputs the integrator refuses: NaN outputs (the tape is not read
+    // beyond its counts)
+    const int st = io.status ? io.status[i] : PN_ST_OK;
+    const double tnt = tp[0], tnw = tp[1];
+    bool ok = st == PN_ST_OK || st == PN_ST_DONE_AT_START;
+    if (st == PN_ST_OK)
+        ok = tnt >= 0.0 && tnw >= 0.0 && tnt + tnw <= (double)u.tape_cap && tnt == __builtin_floor(tnt) &&
+             tnw == __builtin_floor(tnw);
+    ok = ok && m1 > 0.0 && m2 > 0.0 && y[0] > 0.0 && finite(m1) && finite(m2);
+#pragma unroll
+    for (int c = 0; c < 10; ++c) ok = ok && finite(y[c]);
+    if (ok && st == PN_ST_OK) {
+        Row R;
+        make_row(R, m1, m2, u.terms, u.theta_literal);
+        const int nt = (int)tnt;
+        const int N = nt + (int)tnw;
+        const double* hs = tp + 2;
+        for (int k = 0; k < N; ++k) {
+            const bool om = k >= nt;
+            const double h = (om && k == N - 1) ? u.omega_f - y[0] : hs[k];
+            replay_step_t(R, u.tc, y, t, h, om);
+        }
+        if (N > nt) y[0] = u.omega_f;      // the run ends on omega_f exactly
+    } else if (!ok) {
+#pragma unroll
+        for (int c = 0; c < 10; ++c) y[c] = __builtin_nan("");
+        t = __builtin_nan("");
+    }
+#pragma unroll
+    for (int c = 0; c < 10; ++c) io.y[c * ld + i] = y[c];
+    io.t[i] = t;
+}
+
 // Zeroes the work counter of a persistent launch and writes its launch
 // descriptor into the call's slot (one word per thread).
 __global__ void prepare_launch(unsigned long long* slot, LaunchDesc desc) {
@@ -1779,6 +1890,43 @@ int pn_integrate_adjoint(int64_t n, int64_t ld, const double* m, double omega_f,
     io.ws = workspace;                                       // [K][11][n] replayed states and steps
     const int64_t grid = (n + 127) / 128;
     hipLaunchKernelGGL(adjoint_kernel<128>, dim3((unsigned)grid), dim3(128), 0, (hipStream_t)stream, io, u);
+    return hipGetLastError() == hipSuccess ? PN_OK : PN_EHIP;
+}
+
+size_t pn_ckpt_bytes(int64_t n, int64_t cap_steps, int32_t ckpt_every) {
+    if (n < 0 || n > PN_MAX_N || cap_steps < 1 || cap_steps > (1 << 28) || ckpt_every < 1 || ckpt_every > 4096)
+        return 0;
+    return (size_t)n * pn_tape_stride(cap_steps, ckpt_every) * sizeof(double);
+}
+
+int pn_integrate_replay(int64_t n, int64_t ld, const double* m, const double* S0, const double* L0,
+                        const double* omega0, double omega_f, const pn_opts* opt, const double* tape,
+                        int64_t cap_steps, int32_t ckpt_every, const int32_t* status, double* y_final,
+                        double* t_final, void* stream) {
+    if (n < 0 || ld < n || ld > PN_MAX_N) return PN_EINVAL;
+    if (cap_steps < 1 || cap_steps > (1 << 28) || ckpt_every < 1 || ckpt_every > 4096) return PN_EINVAL;
+    if (n > 0 && (!m || !S0 || !L0 || !omega0 || !tape || !y_final || !t_final)) return PN_EINVAL;
+    if (!(omega_f > 0.0 && omega_f < 1e300)) return PN_EINVAL;
+    const int terms = (opt && opt->terms > 0) ? opt->terms : PN_TERM_ALL;
+    const int lit = opt ? opt->theta_literal : 0;
+    if ((opt && opt->terms > PN_TERM_ALL) || (lit != 0 && lit != 1)) return PN_EINVAL;
+    if (opt && (opt->precision != PN_PREC_FP64 || opt->t_end > 0.0 || opt->h_fixed > 0.0)) return PN_EINVAL;
+    if (n == 0) return PN_OK;
+    AdjUni u{};
+    u.omega_f = omega_f;
+    u.tc = term_consts(terms);
+    u.n = n;
+    u.ld = ld;
+    u.terms = terms;
+    u.theta_literal = lit;
+    u.tape = tape;
+    u.tape_stride = (int64_t)pn_tape_stride(cap_steps, ckpt_every);
+    u.tape_cap = (int)cap_steps;
+    u.ckpt_every = ckpt_every;
+    ReplayIo io;
+    io.m = m; io.S0 = S0; io.L0 = L0; io.w0 = omega0; io.status = status; io.y = y_final; io.t = t_final;
+    const int64_t grid = (n + 127) / 128;
+    hipLaunchKernelGGL(replay_kernel<128>, dim3((unsigned)grid), dim3(128), 0, (hipStream_t)stream, io, u);
     return hipGetLastError() == hipSuccess ? PN_OK : PN_EHIP;
 }
 

@@ -114,3 +114,31 @@ def test_cost_order_argument_checks_without_a_device(lib):
     assert call(10, 10, wf=float("nan")) == PN_EINVAL
     assert call(10, 10, ptr=z) == PN_EINVAL
     assert call(0, 0, ptr=z) == PN_OK
+
+
+def test_replay_and_tape_size_checks_without_a_device(lib):
+    from paper_0908_3889_amd._lib import PN_EINVAL, PN_OK, PN_PREC_FP32_SPLIT, PnOpts
+    fake = C.c_void_p(0x1000)       # never dereferenced: validation fails first
+    z = C.c_void_p(0)
+    assert lib.pn_ckpt_bytes(1000, 1024, 16) == 1000 * lib.pn_tape_stride(1024, 16) * 8
+    assert lib.pn_ckpt_bytes(0, 1024, 16) == 0
+    assert lib.pn_ckpt_bytes(-1, 1024, 16) == 0
+    assert lib.pn_ckpt_bytes(10, 0, 16) == 0
+    assert lib.pn_ckpt_bytes(10, 1024, 0) == 0
+
+    def call(n, ld, ptr=fake, wf=0.05, cap=1024, K=16, opt=None):
+        return lib.pn_integrate_replay(n, ld, ptr, ptr, ptr, ptr, wf, opt, ptr, cap, K, None, ptr, ptr, z)
+    assert call(-1, 0) == PN_EINVAL
+    assert call(10, 5) == PN_EINVAL
+    assert call(10, 10, ptr=z) == PN_EINVAL
+    assert call(10, 10, wf=0.0) == PN_EINVAL
+    assert call(10, 10, wf=float("nan")) == PN_EINVAL
+    assert call(10, 10, cap=0) == PN_EINVAL
+    assert call(10, 10, K=0) == PN_EINVAL
+    o = PnOpts()
+    o.precision = PN_PREC_FP32_SPLIT
+    assert call(10, 10, opt=C.byref(o)) == PN_EINVAL
+    o = PnOpts()
+    o.h_fixed = 10.0
+    assert call(10, 10, opt=C.byref(o)) == PN_EINVAL
+    assert call(0, 0, ptr=z) == PN_OK

@@ -340,3 +340,112 @@ def test_central_differences_on_256_samples_of_the_differentiation_workload():
             worst = max(worst, float(err.max()))
     print(f"adjoint vs central differences, 256 samples x 12 components: max rel err {worst:.2e}")
     assert worst < 1e-6
+
+
+# ---------------------------------------------------------------------------
+# pn_integrate_replay: the map the adjoint differentiates, on the GPU
+# ---------------------------------------------------------------------------
+def _gpu_replay(pop, rec, m=None, S=None, L=None, w=None, **kw):
+    from paper_0908_3889_amd import api
+    t = lambda a, b: torch.from_numpy(np.ascontiguousarray(a if a is not None else b)).cuda()
+    r = api.pn_integrate_replay(t(m, pop["m"]), t(S, pop["S"]), t(L, pop["L"]), t(w, pop["omega0"]),
+                                pop["omega_f"], rec, api.make_opts(**kw))
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy() for k, v in r.items()}
+
+
+@pytest.mark.parametrize("workload,n,K", [("adjoint_64k", 300, 16), ("q1to4_1M", 130, 64), ("batching_4M", 65, 1)])
+def test_replay_matches_the_oracle_replay_and_the_recorded_run(workload, n, K):
+    from helpers import normwise_rel
+    pop = P.generate(workload, n)
+    d, rec = _record(pop, K=K, cap=4096)
+    assert (rec["status"].cpu().numpy() == 0).all()
+    r = _gpu_replay(pop, rec)
+    ro = oracle.integrate(pop["m"], pop["S"], pop["L"], pop["omega0"], pop["omega_f"], pop["tol"],
+                          replay=_replay_of(rec), nthreads=8)
+    e_or = normwise_rel(r["y"], ro["y"], pop["S"])
+    e_rec = normwise_rel(r["y"], rec["y"].cpu().numpy(), pop["S"])
+    t_or = np.abs(r["t"] / ro["t"] - 1)
+    t_rec = np.abs(r["t"] / rec["t"].cpu().numpy() - 1)
+    print(f"{workload}: replay vs oracle replay {e_or.max():.2e} (t {t_or.max():.2e}), "
+          f"vs recorded run {e_rec.max():.2e} (t {t_rec.max():.2e})")
+    assert (r["y"][0] == pop["omega_f"]).all()
+    # 1e-12, and on runs beyond 1000 steps 2e-15 per step: two FP64
+    # evaluations of the same map differ by roundings that accumulate with
+    # the steps (measured: at most 1.2e-15 per step on the 4M workload's
+    # adaptive runs of up to 1,575 steps, whose steps are longer than the
+    # fixed-step runs' and amplify a rounding of omega through the
+    # precession phase)
+    steps = rec["steps"].cpu().numpy()[0]
+    bound = np.where(steps > 1000, 2e-15 * steps, 1e-12)
+    print(f"  per step beyond 1000 steps: {(e_or / steps)[steps > 1000].max() if (steps > 1000).any() else 0:.2e}")
+    assert (e_or < bound).all() and (t_or < 1e-12).all()
+    assert (e_rec < bound).all() and (t_rec < 1e-12).all()
+
+
+def test_replay_at_perturbed_inputs_follows_the_oracle_replay():
+    from helpers import normwise_rel
+    pop = P.generate("adjoint_64k", 200)
+    d, rec = _record(pop, K=16)
+    rng = np.random.default_rng(8)
+    S = pop["S"] * (1 + 1e-3 * rng.normal(size=pop["S"].shape))
+    w = pop["omega0"] * (1 + 1e-4 * rng.normal(size=pop["n"]))
+    r = _gpu_replay(pop, rec, S=S, w=w)
+    ro = oracle.integrate(pop["m"], S, pop["L"], w, pop["omega_f"], pop["tol"], replay=_replay_of(rec), nthreads=8)
+    assert normwise_rel(r["y"], ro["y"], S).max() < 1e-12
+    assert np.abs(r["t"] / ro["t"] - 1).max() < 1e-12
+
+
+def test_adjoint_against_central_differences_of_the_gpu_replay():
+    """The same check as against the oracle's replay, with both sides of the
+    difference quotient evaluated by pn_integrate_replay."""
+    n = 64
+    pop = P.generate("adjoint_64k", n)
+    d, rec = _record(pop, K=16)
+    rng = np.random.default_rng(6)
+    gy = rng.normal(size=(10, n))
+    gy[0] = 0.0
+    gt = rng.normal(size=n) * 1e-5
+    g = _adjoint(d, pop, rec, gy, gt)
+
+    def loss(**kw):
+        r = _gpu_replay(pop, rec, **kw)
+        return (gy * r["y"]).sum(0) + gt * r["t"]
+
+    eps = 1e-6
+    worst = 0.0
+    for name, comps, grad, arr in (("m", 2, g["m"], pop["m"]), ("S", 6, g["S0"], pop["S"]),
+                                   ("L", 3, g["L0"], pop["L"]), ("w", 1, g["omega0"][None], pop["omega0"][None])):
+        for c in range(comps):
+            plus, minus = arr.copy(), arr.copy()
+            scale_in = pop["omega0"] if name == "w" else 1.0
+            plus[c] = plus[c] + eps * scale_in
+            minus[c] = minus[c] - eps * scale_in
+            unpack = (lambda a: a[0]) if name == "w" else (lambda a: a)
+            fd = (loss(**{name: unpack(plus)}) - loss(**{name: unpack(minus)})) / (2 * eps)
+            ad = grad[c] * scale_in
+            err = np.abs(fd - ad).max() / max(1.0, np.abs(ad).max())
+            worst = max(worst, err)
+            assert err < 1e-6, (name, c, err)
+    print(f"largest relative FD - adjoint difference {worst:.2e}")
+
+
+def test_replay_of_a_bad_tape_row_gives_nan():
+    pop = P.generate("adjoint_64k", 10)
+    pop["omega0"][9] = pop["omega_f"] * 1.2          # done at start: keeps its initial state
+    d, rec = _record(pop, K=16)
+    assert rec["status"].cpu().numpy()[9] == 1
+    rec = dict(rec)
+    tape = rec["tape"].clone()
+    tape[3, 0] = 0.5                  # not an integer count
+    tape[5, 1] = -1.0                 # negative
+    tape[7, 0] = float(rec["cap_steps"] + 1)
+    rec["tape"] = tape
+    r = _gpu_replay(pop, rec)
+    bad = [3, 5, 7]
+    assert np.isnan(r["y"][:, bad]).all() and np.isnan(r["t"][bad]).all()
+    good = np.setdiff1d(np.arange(10), bad)
+    assert np.isfinite(r["y"][:, good]).all()
+    np.testing.assert_array_equal(r["y"][0, 9], pop["omega0"][9])
+    np.testing.assert_array_equal(r["y"][1:7, 9], pop["S"][:, 9])
+    assert r["t"][9] == 0.0
