@@ -57,10 +57,13 @@
  * and no controller constants.  The error norm and the controller (R7, R8)
  * are pinned by SciPy's RK45, an independent implementation of the same
  * pair and controller, whose accepted time steps and rejections the tests
- * compare with these.  Parity unpinned: the omega stretch (R10), which is
- * pinned only through convergence to closed forms and to an event-located
- * library integration, and the paper's printed correlation coefficients
- * (Sec. V A).
+ * compare with these.  The omega stretch (R10) is one step on every
+ * workload (the first omega-step, the whole distance left, is accepted);
+ * SciPy's RK45 in omega, started from the state after the recorded time
+ * steps, takes the same single step to the same spins, L_hat and t.  The
+ * stretch is also pinned through convergence to closed forms, an
+ * event-located library integration and the paper's printed correlation
+ * coefficients (Sec. V A).
  *
  * The stage sums skip the tableau's structural zeros (a_sj = 0, and
  * b_j = bhat_j = 0 in the error estimate): the method's sums run over the

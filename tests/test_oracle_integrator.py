@@ -388,6 +388,58 @@ def test_step_controller_matches_scipy_rk45(monkeypatch, workload, h0):
         assert r["steps"][1].min() >= 2         # the first step is rejected by the smallest factor
 
 
+def _rhs_in_omega(m, with_t):
+    """dY/domega for Y = (omega, S1, S2, L_hat[, t]): (1, f_1/f_0, ..., f_9/f_0[, 1/f_0])."""
+    def f(w, Y):
+        d = oracle.rhs(m, Y[:10].reshape(10, 1))[:, 0]
+        g = np.concatenate([[1.0], d[1:] / d[0]])
+        return np.concatenate([g, [1.0 / d[0]]]) if with_t else g
+    return f
+
+
+@pytest.mark.parametrize("workload", ["q1to4_1M", "equal_mass_maxspin_1k", "batching_4M", "paper_timing"])
+def test_omega_stretch_matches_scipy_rk45_in_omega(monkeypatch, workload):
+    """The final stretch of reading R10: the time step whose accepted
+    candidate passes omega_f is discarded, and the rest is integrated with
+    omega as the independent variable, dY/domega = f/f_0, by the same
+    Dormand-Prince pair and controller, starting with the whole distance
+    left.  On every workload that first omega-step is accepted, so the
+    stretch is one step from the state after the recorded time steps to
+    omega_f exactly.  SciPy's RK45 started at that state (the recorded time
+    steps replayed), with first_step = omega_f - omega and t_bound = omega_f,
+    must take the same single step and land on the oracle's final spins and
+    L_hat, and, with dt/domega = 1/f_0 carried along, on its t.  A stretch
+    integrated in t, a missing 1/f_0, the state of the discarded step or a
+    first step other than the distance left all fail it."""
+    import scipy.integrate._ivp.rk as rk
+    monkeypatch.setattr(rk, "MAX_FACTOR", 5.0)
+    pop = P.generate(workload, 8)
+    r = oracle.integrate(pop["m"], pop["S"], pop["L"], pop["omega0"], pop["omega_f"], pop["tol"],
+                         record=8192, nthreads=NT)
+    assert (r["status"] == 0).all()
+    n_t, n_w = r["n_tw"]
+    assert (n_w == 1).all()
+    assert (r["y"][0] == pop["omega_f"]).all()
+    # the state after the recorded time steps (replayed: the adaptive run's arithmetic)
+    k = int(n_t.max())
+    sw = oracle.integrate(pop["m"], pop["S"], pop["L"], pop["omega0"], pop["omega_f"], pop["tol"],
+                          replay={"h": np.ascontiguousarray(r["h_record"][:, :k]), "n_t": n_t,
+                                  "n_w": np.zeros_like(n_w)}, nthreads=NT)
+    assert (sw["y"][0] < pop["omega_f"]).all()
+    for i in range(pop["n"]):
+        m = pop["m"][:, i:i + 1]
+        ys, ts, wf = sw["y"][:, i], sw["t"][i], pop["omega_f"]
+        s = si.RK45(_rhs_in_omega(m, False), ys[0], ys, t_bound=wf, first_step=wf - ys[0],
+                    rtol=pop["tol"], atol=pop["tol"])
+        assert s.step() is None and s.status == "finished" and s.t == wf
+        assert s.nfev == 7                      # one attempt (FSAL: 1 + 6 evaluations)
+        assert np.abs(s.y[1:] - r["y"][1:, i]).max() < 1e-13
+        s11 = si.RK45(_rhs_in_omega(m, True), ys[0], np.concatenate([ys, [ts]]), t_bound=wf,
+                      first_step=wf - ys[0], rtol=pop["tol"], atol=pop["tol"])
+        assert s11.step() is None and s11.status == "finished" and s11.nfev == 7
+        assert abs(s11.y[10] / r["t"][i] - 1) < 1e-13
+
+
 # ---------------------------------------------------------------------------
 # Termination and status codes
 # ---------------------------------------------------------------------------
