@@ -855,9 +855,17 @@ __device__ __forceinline__ void persistent_loop(const Uni& u, unsigned long long
             continue;
         }
         // ---- one step on every active lane ----------------------------------------
-        const bool any_w = wave_ballot(active && L.omega_mode) != 0;
-        const int r = P::step(u, L, active, any_w);
-        if (active && r != 0) {
+        // A lane in omega-mode takes its last step (usually one) only once the
+        // wave has enough such lanes and idle lanes to refill right after; it
+        // waits until then as an idle lane would, so that the omega-mode
+        // arithmetic runs in fewer wave-steps.
+        const uint64_t wmask = wave_ballot(active && L.omega_mode);
+        const uint64_t amask = wave_ballot(active);
+        const bool run_w = wmask != 0 && (exhausted || wmask == amask ||
+                                          __popcll(wmask) + (64 - __popcll(amask)) >= u.refill_min);
+        const bool act = active && (run_w || !L.omega_mode);
+        const int r = P::step(u, L, act, run_w);
+        if (act && r != 0) {
             L.h = -(double)(r + kPend);
             active = false;
         }
