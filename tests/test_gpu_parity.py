@@ -175,6 +175,62 @@ def test_adaptive_parity_prefix(workload, n):
     _adaptive_check(pop, run_gpu(pop), run_oracle(pop))
 
 
+def _degenerate_population():
+    """Physical special cases of Eqs. (1)-(4), 8 of each kind, with the 1M
+    workload's masses and frequencies: no spins; one spin zero; both spins
+    along L_hat (a fixed point of the precession); both anti-aligned; equal
+    masses with maximal spins; a start just below omega_f (a run of one
+    omega-step); spins in the orbital plane."""
+    base = P.generate("q1to4_1M", 56)
+    m, S, L, w = base["m"].copy(), base["S"].copy(), base["L"].copy(), base["omega0"].copy()
+    chi1 = np.linalg.norm(S[:3], axis=0) / m[0] ** 2
+    chi2 = np.linalg.norm(S[3:], axis=0) / m[1] ** 2
+    z = np.array([0.0, 0.0, 1.0])[:, None]
+    S[:, 0:8] = 0.0                                            # no spins
+    S[3:, 8:16] = 0.0                                          # S2 = 0
+    S[:3, 16:24] = chi1[16:24] * m[0, 16:24] ** 2 * z          # aligned
+    S[3:, 16:24] = chi2[16:24] * m[1, 16:24] ** 2 * z
+    S[:3, 24:32] = -chi1[24:32] * m[0, 24:32] ** 2 * z         # anti-aligned
+    S[3:, 24:32] = -chi2[24:32] * m[1, 24:32] ** 2 * z
+    m[:, 32:40] = 0.5                                          # equal masses, |chi| = 1
+    S[:3, 32:40] *= 0.25 / np.maximum(np.linalg.norm(S[:3, 32:40], axis=0), 1e-300)
+    S[3:, 32:40] *= 0.25 / np.maximum(np.linalg.norm(S[3:, 32:40], axis=0), 1e-300)
+    w[40:48] = base["omega_f"] * (1 - 1e-6)                   # one omega-step from the start
+    S[2, 48:56] = 0.0                                          # spins in the orbital plane
+    S[5, 48:56] = 0.0
+    pop = dict(base)
+    pop.update(m=m, S=np.ascontiguousarray(S), L=L, omega0=w)
+    return pop
+
+
+def test_adaptive_parity_degenerate_cases():
+    pop = _degenerate_population()
+    rg, ro = run_gpu(pop), run_oracle(pop)
+    assert (ro["status"] == 0).all()
+    _adaptive_check(pop, rg, ro)
+    assert normwise_rel(rg["y"], ro["y"], pop["S"]).max() < 1e-9
+    # no spin, one spin, aligned and anti-aligned: the precession is a fixed point
+    for sl in (slice(0, 8), slice(16, 32)):
+        np.testing.assert_array_equal(rg["y"][1:, sl], np.concatenate([pop["S"], pop["L"]])[:, sl])
+    np.testing.assert_array_equal(rg["y"][4:7, 8:16], 0.0)
+    np.testing.assert_array_equal(rg["dots"][:, 0:8], 0.0)
+    # a start just below omega_f: the time step passes omega_f, so one omega-step
+    assert (rg["steps"][0, 40:48] == 1).all()
+
+
+def test_fixed_step_parity_degenerate_cases():
+    pop = _degenerate_population()
+    ro = run_oracle(pop, h_fixed=100.0)
+    rg = run_gpu(pop, h_fixed=100.0)
+    assert (rg["status"] == ro["status"]).all()
+    np.testing.assert_array_equal(rg["steps"][:2], ro["steps"][:2])
+    steps = ro["steps"][0]
+    err = normwise_rel(rg["y"], ro["y"], pop["S"])
+    print(f"fixed-step degenerate cases: normwise max {err.max():.3e}, steps {steps.min()}..{steps.max()}")
+    # the bar of the fixed-step tests: 1e-12, 1e-15 per step on runs beyond 1000 steps
+    assert (err < np.where(steps > 1000, 1e-15 * steps, 1e-12)).all()
+
+
 def test_adaptive_t_end_parity():
     pop = P.generate("adjoint_64k", 500)
     ro = run_oracle(pop, t_end=12000.0)
