@@ -461,13 +461,17 @@ def bench_study(args, api, stream) -> int:
     import torch
     values = {"m1": [0.5, 0.55, 0.6, 0.65, 0.7, 0.75, 0.8, 0.85, 0.9],
               "chi": [0.1, 0.2, 0.3, 0.4, 0.5, 0.6, 0.7, 0.8, 0.9, 1.0],
-              "omega0": [0.002, 0.003, 0.004, 0.005, 0.006, 0.008, 0.01, 0.015, 0.02]}[args.study]
+              "omega0": [0.002, 0.003, 0.004, 0.005, 0.006, 0.008, 0.01, 0.015, 0.02],
+              "omega_f": [0.03, 0.04, 0.05, 0.06, 0.07, 0.08, 0.1]}[args.study]
+    # --study-case ring: m1 = 0.4, chi = 0.05 (Sec. V D), for the omega0 and omega_f studies
+    fixed = {"m1": 0.4, "chi": 0.05} if args.study_case == "ring" else {}
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    res = api.pearson_study(args.study, values, n=args.study_n, stream=stream)
+    res = api.pearson_study(args.study, values, n=args.study_n, stream=stream, **fixed)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    print(json.dumps({"metric": f"Pearson r (initial vs final) against {args.study}", "n_per_point": args.study_n,
+    print(json.dumps({"metric": f"Pearson r (initial vs final) against {args.study}", "case": args.study_case,
+                      "n_per_point": args.study_n,
                       "values": res["values"], "r_S1S2": res["r"][:, 0].tolist(), "r_S1L": res["r"][:, 1].tolist(),
                       "r_S2L": res["r"][:, 2].tolist(), "all_ok": all(res["ok"]), "seconds": dt}), flush=True)
     return 0
@@ -554,9 +558,11 @@ def main() -> int:
                          "discrete adjoint of loss = sum S1.S2 + sum L_hat_z against the plain forward")
     ap.add_argument("--stats", action="store_true",
                     help="time the statistics stage (histograms, Pearson r, KDE, K-S) on the workload's outputs")
-    ap.add_argument("--study", default=None, choices=["m1", "chi", "omega0"],
-                    help="Pearson r of initial vs final dot products against m1, chi or omega0 (Sec. V B, C, D)")
+    ap.add_argument("--study", default=None, choices=["m1", "chi", "omega0", "omega_f"],
+                    help="Pearson r of initial vs final dot products against m1, chi, omega0 or omega_f (Sec. V B, C, D)")
     ap.add_argument("--study-n", type=int, default=65536)
+    ap.add_argument("--study-case", default="equal", choices=["equal", "ring"],
+                    help="equal: m1 = m2, chi = 1 (Sec. V A set-up); ring: m1 = 0.4, chi = 0.05 (Sec. V D)")
     ap.add_argument("--ks-run", type=int, default=0,
                     help="K-S test of the final S1.S2 over this many inspirals generated on the GPU "
                          "(the paper's run: 362799815)")

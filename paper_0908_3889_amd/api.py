@@ -565,19 +565,26 @@ def initial_dots(d: dict, stream=None) -> torch.Tensor:
     return pn_observables(y0, stream=stream)
 
 
-def pearson_study(kind: str, values, n: int = 16384, base: str = "paper_equal_mass", stream=None) -> dict:
-    """The parameter studies of Sec. V B and C: for each value, a population of
-    n inspirals of the base workload with m1 = value (chi_1 = chi_2 = 1),
-    chi_1 = chi_2 = value (m1 = m2) or omega0 = value (the base workload
-    otherwise), integrated on the GPU, and the Pearson r
-    of initial against final S1.S2, S1.L, S2.L.  Returns {"values", "r" [k, 3],
-    "ok" [k]}."""
+def pearson_study(kind: str, values, n: int = 16384, base="paper_equal_mass", m1: float | None = None,
+                  chi: float | None = None, stream=None) -> dict:
+    """The parameter studies of Sec. V B-D: for each value, a population of n
+    inspirals of the base workload (a name in population.WORKLOADS or a
+    Workload) with m1 = value (chi_1 = chi_2 = 1), chi_1 = chi_2 = value
+    (m1 = m2), omega0 = value or omega_f = value, integrated on the GPU, and
+    the Pearson r of initial against final S1.S2, S1.L, S2.L.  m1 and chi, if
+    given, are held at those values first (for instance m1 = 0.4, chi = 0.05,
+    the case of Sec. V D whose correlations depend on omega0 and omega_f).
+    Returns {"values", "r" [k, 3], "ok" [k]}."""
     import dataclasses
 
     import numpy as np
 
     from . import population
-    w0 = population.WORKLOADS[base]
+    w0 = base if isinstance(base, population.Workload) else population.WORKLOADS[base]
+    if m1 is not None:
+        w0 = dataclasses.replace(w0, q=("fixed", float(m1) / (1.0 - float(m1))))
+    if chi is not None:
+        w0 = dataclasses.replace(w0, chi=("fixed", float(chi), float(chi)))
     rs, oks = [], []
     for v in values:
         if kind == "m1":
@@ -586,8 +593,10 @@ def pearson_study(kind: str, values, n: int = 16384, base: str = "paper_equal_ma
             w = dataclasses.replace(w0, q=("fixed", 1.0), chi=("fixed", float(v), float(v)))
         elif kind == "omega0":
             w = dataclasses.replace(w0, omega0=("fixed", float(v)))
+        elif kind == "omega_f":
+            w = dataclasses.replace(w0, omega_f=float(v))
         else:
-            raise ValueError("kind is 'm1', 'chi' or 'omega0'")
+            raise ValueError("kind is 'm1', 'chi', 'omega0' or 'omega_f'")
         pop = population.generate(w, n)
         d = to_device(pop)
         out = pn_integrate(d["m"], d["S"], d["L"], d["omega0"], pop["omega_f"], pop["tol"], stream=stream)
