@@ -136,14 +136,10 @@ PROFILES = os.path.join(ROOT, "profiles")
 COPY_CAL_BYTES = 512 << 20
 
 
-def measured_traffic(kernel: str, workload: str):
-    """HBM bytes per launch of `kernel` on `workload`, from the committed
-    counter summary profiles/hbm_<kernel>_<workload>.txt (FETCH_SIZE and
-    WRITE_SIZE, each scaled by what the counter reads for a plain copy of known
-    size).  None when there is no such summary or the device sources have
-    changed since the counters were taken."""
+def _profile_field(path: str, key: str):
+    """A numeric field of a committed counter summary, or None when the file
+    is missing or the device sources have changed since it was taken."""
     from paper_0908_3889_amd import build
-    path = os.path.join(PROFILES, f"hbm_{kernel}_{workload}.txt")
     if not os.path.exists(path):
         return None
     fields = {}
@@ -154,9 +150,26 @@ def measured_traffic(kernel: str, workload: str):
     if fields.get("source_digest") != build.source_digest():
         return None
     try:
-        return float(fields["hbm_bytes_per_launch"])
+        return float(fields[key])
     except (KeyError, ValueError):
         return None
+
+
+def measured_counter_flop(kernel: str, workload: str):
+    """FP64 lane FLOPs executed per launch of `kernel` on `workload`, from the
+    committed summary profiles/flops_<kernel>_<workload>.txt (rocprofv3's
+    SQ_INSTS_VALU_FLOPS_FP64 times the active lanes per VALU instruction,
+    calibrated on launches with a known number of active lanes)."""
+    return _profile_field(os.path.join(PROFILES, f"flops_{kernel}_{workload}.txt"), "counter_flop_per_launch")
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` on `workload`, from the committed
+    counter summary profiles/hbm_<kernel>_<workload>.txt (FETCH_SIZE and
+    WRITE_SIZE, each scaled by what the counter reads for a plain copy of known
+    size).  None when there is no such summary or the device sources have
+    changed since the counters were taken."""
+    return _profile_field(os.path.join(PROFILES, f"hbm_{kernel}_{workload}.txt"), "hbm_bytes_per_launch")
 
 
 def kernel_resources(kernel: str, block: int):
@@ -190,6 +203,16 @@ def calibrate_copy() -> int:
         b.copy_(a)
     torch.cuda.synchronize()
     print(json.dumps({"copy_bytes": COPY_CAL_BYTES, "copies": 3}), flush=True)
+    return 0
+
+
+def calibrate_lanes() -> int:
+    """FP64 FMA chains on 64, 32, 16, 4 and 1 active lanes per wave, one launch
+    each in that order (the reference launches for reading FLOP and
+    thread-cycle counters on partly active waves)."""
+    from paper_0908_3889_amd import api
+    runs = [api.pn_fma_lanes(k, 2000) for k in (64, 32, 16, 4, 1)]
+    print(json.dumps({"calibrate_lanes": runs}), flush=True)
     return 0
 
 
@@ -568,6 +591,8 @@ def main() -> int:
                          "(the paper's run: 362799815)")
     ap.add_argument("--sweep", action="store_true",
                     help="throughput against n = 2^8 .. 2^22, replicated and heterogeneous inspirals")
+    ap.add_argument("--calibrate-lanes", action="store_true",
+                    help="only run FP64 FMA chains on 64, 32, 16, 4 and 1 active lanes per wave (counter calibration)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run three plain device copies of 512 MiB (counter calibration)")
     ap.add_argument("--phase", action="store_true",
@@ -590,6 +615,8 @@ def main() -> int:
 
     if args.calibrate_copy:
         return calibrate_copy()
+    if args.calibrate_lanes:
+        return calibrate_lanes()
 
     from paper_0908_3889_amd import api, population
 
@@ -672,6 +699,7 @@ def main() -> int:
     kernel = (f"integrate_{args.schedule}_{ {'fp64': 'f64', 'fp32split': 'f32s', 'fp32': 'f32x'}[precision] }"
               + ("_phase" if args.phase else ""))
     traffic = measured_traffic(kernel, w.name)
+    counter_flop = measured_counter_flop(kernel, w.name)
     resources = kernel_resources(kernel, opts.block or 256)
     res = {
         "metric": METRIC,
@@ -699,7 +727,9 @@ def main() -> int:
                      "frac_at_oracle_count": algorithmic_flops(steps, ORACLE_F_RHS, ORACLE_F_STEP_COMB)
                      / (avg_ms * 1e-3) / 1e12 / peak,
                      "frac_at_1300_per_attempted_step": attempted_steps(steps) * PLAN_F_STEP
-                     / (avg_ms * 1e-3) / 1e12 / peak},
+                     / (avg_ms * 1e-3) / 1e12 / peak,
+                     "counter_achieved": (counter_flop / (avg_ms * 1e-3) / 1e12) if counter_flop else None,
+                     "counter_frac": (counter_flop / (avg_ms * 1e-3) / 1e12 / peak) if counter_flop else None},
         "kernel": kernel,
         "kernel_resources": resources,
         "launch": {"block": opts.block or 256, "refill_min": opts.refill_min or 4,

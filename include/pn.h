@@ -332,6 +332,18 @@ int pn_shutdown(void);
 int pn_fma_rate(int32_t waves_per_simd, int32_t iters, double* fp32_tflops, double* fp64_tflops, void* stream);
 
 /*
+ * pn_fma_lanes -- the FP64 chains of pn_fma_rate on the first active_lanes
+ * (0..64) lanes of every wave only, one wave per SIMD (one block of 256 per
+ * CU), once: a launch whose lane FLOPs are known, for calibrating instruction
+ * and FLOP counters on partly active waves (a profiler reads the counters;
+ * the library only launches).  Writes the lane FLOPs of the launch (an FMA
+ * counted as 2) to *lane_flop and its duration to *ms (host pointers).
+ * Allocates and frees a small device buffer and blocks until the timer is
+ * read.
+ */
+int pn_fma_lanes(int32_t active_lanes, int32_t iters, double* lane_flop, double* ms, void* stream);
+
+/*
  * pn_rhs -- Eqs. (1)-(4) evaluated pointwise, dy/dt at y, for testing the
  * right-hand side on its own.  m [2][ld], y [10][ld] -> dydt [10][ld].
  * `terms`/`theta_literal` as in pn_opts (opt may be NULL).

@@ -30,7 +30,7 @@ EXPORTS = ("pn_integrate", "pn_rhs", "pn_observables", "pn_strerror", "pn_versio
            "pn_ks_workspace_bytes", "pn_ks_uniform", "pn_stats_workspace_bytes", "pn_generate",
            "pn_autotune", "pn_integrate_phase", "pn_fma_rate", "pn_shutdown", "pn_integrate_noalloc", "pn_cost_order", "pn_cost_order_workspace_bytes",
            "pn_check_integrate_host", "pn_check_start", "pn_check_finish", "pn_ckpt_bytes",
-           "pn_integrate_replay")
+           "pn_integrate_replay", "pn_fma_lanes")
 
 
 class PnOpts(C.Structure):
@@ -117,6 +117,8 @@ def load():
     L.pn_integrate_adjoint.argtypes = [i64, i64, vp, dbl, popts, vp, i64, C.c_int32, vp, vp, vp, vp, vp,
                                        vp, vp, vp, C.c_size_t, vp, vp]
     L.pn_integrate_adjoint.restype = C.c_int
+    L.pn_fma_lanes.argtypes = [C.c_int32, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double), vp]
+    L.pn_fma_lanes.restype = C.c_int
     L.pn_ckpt_bytes.argtypes = [i64, i64, C.c_int32]
     L.pn_ckpt_bytes.restype = C.c_size_t
     L.pn_integrate_replay.argtypes = [i64, i64, vp, vp, vp, vp, dbl, popts, vp, i64, C.c_int32, vp, vp, vp, vp]

@@ -419,6 +419,15 @@ def pn_shutdown() -> None:
     check(load().pn_shutdown(), "pn_shutdown")
 
 
+def pn_fma_lanes(active_lanes: int, iters: int = 4000, stream=None) -> dict:
+    """One launch of FP64 FMA chains on the first active_lanes lanes of every
+    wave (one wave per SIMD): its lane FLOPs and duration."""
+    flop, ms = C.c_double(), C.c_double()
+    rc = load().pn_fma_lanes(int(active_lanes), int(iters), C.byref(flop), C.byref(ms), _stream(stream))
+    check(rc, "pn_fma_lanes")
+    return {"active_lanes": int(active_lanes), "lane_flop": flop.value, "ms": ms.value}
+
+
 def pn_fma_rate(waves_per_simd: int = 8, iters: int = 4000, stream=None) -> dict:
     """Sustained vector FMA rate of the current device in TFLOP/s: FP32
     without packed instructions, and FP64 (blocks until measured)."""

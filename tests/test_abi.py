@@ -142,3 +142,12 @@ def test_replay_and_tape_size_checks_without_a_device(lib):
     o.h_fixed = 10.0
     assert call(10, 10, opt=C.byref(o)) == PN_EINVAL
     assert call(0, 0, ptr=z) == PN_OK
+
+
+def test_fma_lanes_argument_checks_without_a_device(lib):
+    from paper_0908_3889_amd._lib import PN_EINVAL
+    d = C.c_double()
+    assert lib.pn_fma_lanes(-1, 10, C.byref(d), C.byref(d), None) == PN_EINVAL
+    assert lib.pn_fma_lanes(65, 10, C.byref(d), C.byref(d), None) == PN_EINVAL
+    assert lib.pn_fma_lanes(8, 0, C.byref(d), C.byref(d), None) == PN_EINVAL
+    assert lib.pn_fma_lanes(8, 10, None, C.byref(d), None) == PN_EINVAL
