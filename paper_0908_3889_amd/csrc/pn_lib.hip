@@ -147,16 +147,69 @@ __device__ int read_input(const Io& io, const Uni& u, int64_t idx, double* y, do
     return 0;
 }
 
-// mean_c (e_c / (tol + tol max(|y_c|, |ynew_c|)))^2: the squared RMS error norm
-// z = err^2 of the error estimate e (the FP64 stepper passes e/h and scales
-// the result by h^2)
-__device__ __forceinline__ double error_norm(const Uni& u, const double* y, const double* ynew, const double* e) {
+// mean_c (e_c / sc_c)^2 with sc_c = tol + tol max(|y_c|, |ynew_c|): the squared
+// RMS error norm z = err^2 of the error estimate e (the FP64 stepper passes
+// e/h and scales the result by h^2).  One reciprocal per component: the FP32
+// modes, whose tighter register budget the grouped form below would spill.
+__device__ __forceinline__ double error_norm_each(const Uni& u, const double* y, const double* ynew, const double* e) {
     double z = 0.0;
 #pragma unroll
     for (int c = 0; c < 10; ++c) {
         const double sc = __builtin_fma(u.tol, fmax_abs(y[c], ynew[c]), u.tol);
         const double q = e[c] * rcp_1step(sc);
         z = __builtin_fma(q, q, z);
+    }
+    return z * 0.1;
+}
+
+// 1/s0 .. 1/s3 from the reciprocal of their product (1/s0 = s1 s2 s3 / (s0 s1
+// s2 s3), and so on); bad is set when the product is not a positive normal
+// number, where that reciprocal cannot be trusted.
+__device__ __forceinline__ void rcp4(double s0, double s1, double s2, double s3, double& i0, double& i1,
+                                     double& i2, double& i3, bool& bad) {
+    const double p01 = s0 * s1, p23 = s2 * s3;
+    const double P = p01 * p23;
+    bad = bad || __builtin_amdgcn_class(P, 0x2ff);   // every class but +normal
+    const double r = rcp_1step(P);
+    const double r01 = r * p23, r23 = r * p01;
+    i0 = r01 * s1; i1 = r01 * s0; i2 = r23 * s3; i3 = r23 * s2;
+}
+
+// The same norm (FP64 stepper) with the ten reciprocals taken in groups of
+// four, four and two.  FP64 reciprocals issue at a quarter of the FMA rate:
+// three of them and 15 multiplications cost less than ten, and the result
+// differs from one reciprocal per component by a few ulp.  Lanes with a group
+// product outside the normal range (tolerances or states far beyond double
+// precision) take one reciprocal per component instead.
+__device__ __forceinline__ double error_norm(const Uni& u, const double* y, const double* ynew, const double* e) {
+    double sc[10], iv[10];
+#pragma unroll
+    for (int c = 0; c < 10; ++c) sc[c] = __builtin_fma(u.tol, fmax_abs(y[c], ynew[c]), u.tol);
+    bool bad = false;
+    rcp4(sc[0], sc[1], sc[2], sc[3], iv[0], iv[1], iv[2], iv[3], bad);
+    rcp4(sc[4], sc[5], sc[6], sc[7], iv[4], iv[5], iv[6], iv[7], bad);
+    {
+        const double p = sc[8] * sc[9];
+        bad = bad || __builtin_amdgcn_class(p, 0x2ff);
+        const double r = rcp_1step(p);
+        iv[8] = r * sc[9];
+        iv[9] = r * sc[8];
+    }
+    double z = 0.0;
+#pragma unroll
+    for (int c = 0; c < 10; ++c) {
+        const double q = e[c] * iv[c];
+        z = __builtin_fma(q, q, z);
+    }
+    if (__builtin_expect(__ballot(bad) != 0, 0)) {
+        if (bad) {
+            z = 0.0;
+#pragma unroll
+            for (int c = 0; c < 10; ++c) {
+                const double q = e[c] * rcp_1step(sc[c]);
+                z = __builtin_fma(q, q, z);
+            }
+        }
     }
     return z * 0.1;
 }
@@ -574,7 +627,7 @@ struct F32Split {
         double e[10];
 #pragma unroll
         for (int c = 0; c < 10; ++c) e[c] = (double)(hf * __builtin_fmaf((float)E7, k7[c], Ep[c]));
-        const double z = error_norm(u, L.y, ynew, e);
+        const double z = error_norm_each(u, L.y, ynew, e);
         bool fin = (GEN && u.fixed) || !__builtin_isnan(z);
 #pragma unroll
         for (int c = 0; c < 10; ++c) fin = fin && finite(ynew[c]) && __builtin_isfinite(k7[c]);
@@ -762,7 +815,7 @@ struct F32State {
         double e[10];
 #pragma unroll
         for (int c = 0; c < 10; ++c) e[c] = (double)(hf * __builtin_fmaf((float)E7, k7[c], Ep[c]));
-        const double z = error_norm(u, yd, ynew, e);
+        const double z = error_norm_each(u, yd, ynew, e);
         bool fin = (GEN && u.fixed) || !__builtin_isnan(z);
 #pragma unroll
         for (int c = 0; c < 10; ++c) fin = fin && finite(ynew[c]) && __builtin_isfinite(k7[c]);
