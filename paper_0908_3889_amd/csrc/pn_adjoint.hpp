@@ -13,9 +13,10 @@ struct RowBar {
     double v[NROW];
 };
 
-// VJP of f = rhs(y) at y: given fbar = dL/df (10), adds (df/dy)^T fbar to
-// ybar and (df/drow)^T fbar to rb.  The primal is recomputed here (same
-// expansion as rhs(), with the full cube root and log).
+// VJP of f = rhs(y) at y: given fbar = dL/df (10), writes (df/dy)^T fbar to
+// ybar and adds (df/drow)^T fbar to rb.  The primal is recomputed here (same
+// expansion as rhs(); the cube root and log of the stage from the step's base
+// point lb, as the stage derivatives of the replay take them).
 //
 // Omega mode: the stage derivative is g = (1, f_1/f_0, ..., f_9/f_0) with
 // dt/domega = 1/f_0.  With omega_mode set, gbar (slot 0 unused) and gtbar
@@ -24,15 +25,16 @@ struct RowBar {
 //   fbar_c = gbar_c s (c >= 1),  fbar_0 = -s^2 sbar.
 //
 // gscale multiplies gbar_in (the step size of the RK adjoint recurrence).
-__device__ __forceinline__ void rhs_vjp(const Row& r, const TermConsts& tc, const double* __restrict__ y,
+__device__ __forceinline__ void rhs_vjp(const Row& r, const TermConsts& tc, const LogBase& lb,
+                                        const double* __restrict__ y,
                                         const double* __restrict__ gbar_in, double gscale, double gtbar,
                                         bool omega_mode, double* __restrict__ ybar, RowBar& rb) {
     // ---------------- primal ----------------
     const double w = y[0];
     const double M = r[R_M];
     const double v = M * w;
-    const double x = cbrt_real(v);
-    const double lnv = log_pos(__builtin_fabs(v));
+    double x, lnv;
+    stage_x_lnv(lb, v, w, x, lnv);
     const double x2 = x * x;
     const double L0 = y[7], L1 = y[8], L2 = y[9];
     const double a0 = y[1], a1 = y[2], a2 = y[3];
@@ -229,10 +231,10 @@ __device__ __forceinline__ void rhs_vjp(const Row& r, const TermConsts& tc, cons
     rb.v[R_M] = __builtin_fma(w, vbar, rb.v[R_M]);
     wbar = __builtin_fma(M, vbar, wbar);
 
-    ybar[0] += wbar;
-    ybar[1] += ab0; ybar[2] += ab1; ybar[3] += ab2;
-    ybar[4] += bb0; ybar[5] += bb1; ybar[6] += bb2;
-    ybar[7] += Lb0; ybar[8] += Lb1; ybar[9] += Lb2;
+    ybar[0] = wbar;
+    ybar[1] = ab0; ybar[2] = ab1; ybar[3] = ab2;
+    ybar[4] = bb0; ybar[5] = bb1; ybar[6] = bb2;
+    ybar[7] = Lb0; ybar[8] = Lb1; ybar[9] = Lb2;
 #undef a0
 #undef a1
 #undef a2

@@ -1128,19 +1128,27 @@ __device__ __forceinline__ void replay_step(const Row& R, const TermConsts& tc, 
 // lt is dL/dt (constant along the path).  `last` marks the last omega-step,
 // whose size D = omega_f - omega depends on the state: it adds -dL/dD to
 // lam[0].
-//   ys: the state before the step (slot 0, filled by the caller) and the
-//       stage points Y_2..Y_6 (slots 1..5) of this lane in LDS; entry (s, c)
-//       at ys[(s * 10 + c) * 64];
+//   ys: this lane's LDS rows, entry (s, c) at ys[(s * 10 + c) * 64]: the state
+//       before the step (slot 0, filled by the caller), the stage points
+//       Y_2..Y_6 (slots 1..5; each replaced by its stage adjoint mu_j once
+//       stage j is reversed), and the step's log base (slot 6, entries 0..3);
 //   pf: the state and step size of the step reversed next (workspace column,
-//       entry c at pf[c * pfstride]), parked in nx (LDS, entry c at nx[c * 64]);
-//   the stage adjoints mu_2..mu_6 stay in registers.
+//       entry c at pf[c * pfstride]), parked in nx (LDS, entry c at nx[c * 64]).
+// What stays in registers across the stages is the row, its adjoint, lambda
+// and the stage being reversed: at one wave per SIMD these fit in the 256
+// VGPRs and the AGPRs without scratch.
 __device__ __forceinline__ void reverse_step(const Row& R, const TermConsts& tc, double h, bool om, bool last,
                                              double* lam, double lt, RowBar& rb, double* __restrict__ ys,
                                              const double* __restrict__ pf, int64_t pfstride,
                                              double* __restrict__ nx) {
 #define YS(S, C) ys[((S) * 10 + (C)) * 64]
-    double mreg[5][10];
-#define MS(J, C) mreg[J][C]
+    // mu_j (j = 2..6) goes to the LDS slot of Y_j once stage j is reversed
+    // (Y_j is dead then) and is read back through a pointer the compiler
+    // cannot see through (the empty asm after each stage), so that the
+    // values are not kept in registers instead
+    typedef __attribute__((address_space(3))) double lds_double;
+    lds_double* ml = (lds_double*)ys;
+#define MS(J, C) ml[(((J) + 1) * 10 + (C)) * 64]
     const LogBase lb{};
     {
         double y[10];
@@ -1154,6 +1162,7 @@ __device__ __forceinline__ void reverse_step(const Row& R, const TermConsts& tc,
         for (int c = 0; c < 11; ++c) nxt[c] = pf[c * pfstride];
         double k1[10], k2[10], k3[10], k4[10], k5[10], Y[10];
         const LogBase lbs = log_base(R, y);
+        YS(6, 0) = lbs.lnv; YS(6, 1) = lbs.x; YS(6, 2) = lbs.w; YS(6, 3) = lbs.iw;
         stage_deriv(R, tc, lbs, y, k1, om);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -1193,9 +1202,7 @@ __device__ __forceinline__ void reverse_step(const Row& R, const TermConsts& tc,
     }
 
     // reverse: stage i = 6 .. 1; mu_j (j > i) read back from LDS
-    double lnew[10];
-#pragma unroll
-    for (int c = 0; c < 10; ++c) lnew[c] = lam[c];
+    double mu1[10];      // mu_1 (the others are in LDS)
     double dh = 0.0;     // dL/dh (last omega-step only)
 
     // Lh = b_i lam + sum_{j>i} a_ji mu_j ; the VJP is seeded with h Lh
@@ -1205,9 +1212,14 @@ __device__ __forceinline__ void reverse_step(const Row& R, const TermConsts& tc,
         _Pragma("unroll") for (int c = 0; c < 10; ++c) {                                         \
             Yi[c] = YS(SLOT, c);                                                                 \
             Lh[c] = (LAMEXPR);                                                                   \
-            mu[c] = 0.0;                                                                         \
         }                                                                                        \
-        rhs_vjp(R, tc, Yi, Lh, h, lt * h * (BI), om, mu, rb);                                       \
+        const LogBase lbv{ml[(60) * 64], ml[(61) * 64], ml[(62) * 64], ml[(63) * 64]};              \
+        rhs_vjp(R, tc, lbv, Yi, Lh, h, lt * h * (BI), om, mu, rb);                                       \
+        /* the row adjoint's updates are completed here: left to itself the */                 \
+        /* compiler defers them to the end of the step and keeps every */                         \
+        /* stage's operands alive until then (~700 AGPR moves and scratch */                      \
+        /* spills per step) */                                                                   \
+        _Pragma("unroll") for (int i = 0; i < NROW; ++i) __asm__ volatile("" : "+v"(rb.v[i]));   \
         if (last) {                                                                              \
             double f[10];                                                                        \
             rhs<Row, false>(R, tc, lb, Yi, f);                                                   \
@@ -1217,9 +1229,10 @@ __device__ __forceinline__ void reverse_step(const Row& R, const TermConsts& tc,
             dh += dot + lt * (BI) * s;                                                           \
         }                                                                                        \
         _Pragma("unroll") for (int c = 0; c < 10; ++c) {                                         \
-            lnew[c] += mu[c];                                                                    \
+            if ((MUJ) < 0) mu1[c] = mu[c];                                                       \
             if ((MUJ) >= 0) MS((MUJ) >= 0 ? (MUJ) : 0, c) = mu[c];                               \
         }                                                                                        \
+        __asm__ volatile("" : "+v"(ml));                                                          \
         __builtin_amdgcn_sched_barrier(0);                                                       \
     }
 
@@ -1233,11 +1246,13 @@ __device__ __forceinline__ void reverse_step(const Row& R, const TermConsts& tc,
     PN_REV_STAGE(0, B1, -1, __builtin_fma(A61, MS(4, c), __builtin_fma(A51, MS(3, c), __builtin_fma(A41, MS(2, c),
                               __builtin_fma(A31, MS(1, c), __builtin_fma(A21, MS(0, c), B1 * lam[c]))))))
 #undef PN_REV_STAGE
+    // lambda_n = lambda_{n+1} + mu_6 + ... + mu_1 (in the order the stages are reversed)
+#pragma unroll
+    for (int c = 0; c < 10; ++c)
+        lam[c] = ((((lam[c] + MS(4, c)) + MS(3, c)) + MS(2, c)) + MS(1, c)) + MS(0, c) + mu1[c];
 #undef YS
 #undef MS
 
-#pragma unroll
-    for (int c = 0; c < 10; ++c) lam[c] = lnew[c];
     if (last) lam[0] -= dh;
 }
 
@@ -1353,7 +1368,7 @@ __device__ void adjoint_one(const AdjIo& io, const AdjUni& u, int64_t idx, doubl
 
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void adjoint_kernel(AdjIo io, AdjUni u) {
-    __shared__ double s_ys[BLOCK / 64][60][64];     // y and the stage points of each lane
+    __shared__ double s_ys[BLOCK / 64][64][64];     // y, the stage points and the step's log base
     double* ys = &s_ys[threadIdx.x / 64][0][lane_id()];
     __shared__ double s_nx[BLOCK / 64][11][64];     // state and step size of the step reversed next
     double* nx = &s_nx[threadIdx.x / 64][0][lane_id()];
