@@ -36,3 +36,28 @@ def test_device_code_has_no_packed_fp32(source, tmp_path):
     assert ".amdgcn_target" in asm or "amdgcn" in asm
     hits = PACKED.findall(asm)
     assert not hits, f"{len(hits)} packed FP32 instructions in {source}"
+
+
+def _resources(pattern):
+    res = build.resource_usage()
+    if not res:
+        pytest.skip("library not built (no resource report)")
+    hits = {k: v for k, v in res.items() if pattern in k}
+    assert hits, pattern
+    return hits
+
+
+def test_hot_kernels_keep_their_register_budget():
+    """The FP64 integration kernel runs at 2 waves per SIMD with at most the
+    12 B of scratch its refill-pass constant takes; the backward kernel of
+    the adjoint fits its registers without scratch (a regression here is the
+    compiler deferring the row-adjoint updates again)."""
+    for name, r in _resources("integrate_persistent_f64ILi256ELb0E").items():
+        assert int(r["Occupancy [waves/SIMD]"]) == 2, name
+        assert int(r["ScratchSize [bytes/lane]"]) <= 12, name
+    for name, r in _resources("adjoint_kernelILi128").items():
+        assert int(r["ScratchSize [bytes/lane]"]) == 0, name
+        assert int(r["VGPRs Spill"]) == 0, name
+        assert int(r["LDS Size [bytes/block]"]) <= 80 * 1024, name
+    for name, r in _resources("integrate_persistent_f32sILi256E").items():
+        assert int(r["Occupancy [waves/SIMD]"]) == 3 and int(r["ScratchSize [bytes/lane]"]) == 0, name
