@@ -98,6 +98,11 @@ static_assert(sizeof(LaunchDesc) % 8 == 0 && sizeof(LaunchDesc) / 8 <= 64, "desc
 
 __device__ __forceinline__ bool finite(double v) { return __builtin_isfinite(v); }
 
+// An empty asm that takes v in a register: the accumulation that produced v is
+// completed here instead of being deferred (with its operands kept alive).
+__device__ __forceinline__ void settle(double& v) { __asm__ volatile("" : "+v"(v)); }
+__device__ __forceinline__ void settle(float& v) { __asm__ volatile("" : "+v"(v)); }
+
 template <bool PHASE = false>
 __device__ void write_out(const Io& io, const Uni& u, int64_t i, const double* y, double t, int acc,
                           int rej, int nrhs, int st, double phase = 0.0) {
@@ -417,8 +422,8 @@ struct F64 {
 #pragma unroll
             for (int c = 0; c < 10; ++c) Y[c] = __builtin_fma(c2, k2[c], __builtin_fma(c1, k1[c], y[c]));
             rhs<Row, true>(R, u.tc, lb, Y, k3);
-            if (__builtin_expect(any_w, 0)) { to_omega_variable(k3, dtj, L.omega_mode); dts = __builtin_fma(B3, dtj, dts); }
-            if (PHASE) ps = __builtin_fma(B3, Y[0] * (any_w ? dtj : 1.0), ps);
+            if (__builtin_expect(any_w, 0)) { to_omega_variable(k3, dtj, L.omega_mode); dts = __builtin_fma(B3, dtj, dts); settle(dts); }
+            if (PHASE) { ps = __builtin_fma(B3, Y[0] * (any_w ? dtj : 1.0), ps); settle(ps); }
         }
         {
             const double c1 = h * A41, c2 = h * A42, c3 = h * A43;
@@ -426,8 +431,8 @@ struct F64 {
             for (int c = 0; c < 10; ++c)
                 Y[c] = __builtin_fma(c3, k3[c], __builtin_fma(c2, k2[c], __builtin_fma(c1, k1[c], y[c])));
             rhs<Row, true>(R, u.tc, lb, Y, k4);
-            if (__builtin_expect(any_w, 0)) { to_omega_variable(k4, dtj, L.omega_mode); dts = __builtin_fma(B4, dtj, dts); }
-            if (PHASE) ps = __builtin_fma(B4, Y[0] * (any_w ? dtj : 1.0), ps);
+            if (__builtin_expect(any_w, 0)) { to_omega_variable(k4, dtj, L.omega_mode); dts = __builtin_fma(B4, dtj, dts); settle(dts); }
+            if (PHASE) { ps = __builtin_fma(B4, Y[0] * (any_w ? dtj : 1.0), ps); settle(ps); }
         }
         {
             const double c1 = h * A51, c2 = h * A52, c3 = h * A53, c4 = h * A54;
@@ -436,8 +441,8 @@ struct F64 {
                 Y[c] = __builtin_fma(c4, k4[c], __builtin_fma(c3, k3[c],
                        __builtin_fma(c2, k2[c], __builtin_fma(c1, k1[c], y[c]))));
             rhs<Row, true>(R, u.tc, lb, Y, k5);
-            if (__builtin_expect(any_w, 0)) { to_omega_variable(k5, dtj, L.omega_mode); dts = __builtin_fma(B5, dtj, dts); }
-            if (PHASE) ps = __builtin_fma(B5, Y[0] * (any_w ? dtj : 1.0), ps);
+            if (__builtin_expect(any_w, 0)) { to_omega_variable(k5, dtj, L.omega_mode); dts = __builtin_fma(B5, dtj, dts); settle(dts); }
+            if (PHASE) { ps = __builtin_fma(B5, Y[0] * (any_w ? dtj : 1.0), ps); settle(ps); }
         }
         {
             const double c1 = h * A61, c2 = h * A62, c3 = h * A63, c4 = h * A64, c5 = h * A65;
@@ -446,8 +451,8 @@ struct F64 {
                 Y[c] = __builtin_fma(c5, k5[c], __builtin_fma(c4, k4[c], __builtin_fma(c3, k3[c],
                        __builtin_fma(c2, k2[c], __builtin_fma(c1, k1[c], y[c])))));
             rhs<Row, true>(R, u.tc, lb, Y, k6);
-            if (__builtin_expect(any_w, 0)) { to_omega_variable(k6, dtj, L.omega_mode); dts = __builtin_fma(B6, dtj, dts); }
-            if (PHASE) ps = __builtin_fma(B6, Y[0] * (any_w ? dtj : 1.0), ps);
+            if (__builtin_expect(any_w, 0)) { to_omega_variable(k6, dtj, L.omega_mode); dts = __builtin_fma(B6, dtj, dts); settle(dts); }
+            if (PHASE) { ps = __builtin_fma(B6, Y[0] * (any_w ? dtj : 1.0), ps); settle(ps); }
         }
         // stage 7 point = 5th-order solution; the error sum over k1, k3..k6 is
         // formed now so that those vectors die before the last RHS
@@ -572,8 +577,8 @@ struct F32Split {
 #pragma unroll
             for (int c = 0; c < 10; ++c) Y[c] = __builtin_fmaf(c2, k2[c], __builtin_fmaf(c1, k1[c], yf[c]));
             rhs_f32(R, u.tcf, Y, k3);
-            if (__builtin_expect(any_w, 0)) { to_omega_variable(k3, dtj, L.omega_mode); dts = __builtin_fmaf((float)B3, dtj, dts); }
-            if (PHASE) ps = __builtin_fmaf((float)B3, Y[0] * (any_w ? dtj : 1.0f), ps);
+            if (__builtin_expect(any_w, 0)) { to_omega_variable(k3, dtj, L.omega_mode); dts = __builtin_fmaf((float)B3, dtj, dts); settle(dts); }
+            if (PHASE) { ps = __builtin_fmaf((float)B3, Y[0] * (any_w ? dtj : 1.0f), ps); settle(ps); }
         }
         {
             const float c1 = hf * (float)A41, c2 = hf * (float)A42, c3 = hf * (float)A43;
@@ -581,8 +586,8 @@ struct F32Split {
             for (int c = 0; c < 10; ++c)
                 Y[c] = __builtin_fmaf(c3, k3[c], __builtin_fmaf(c2, k2[c], __builtin_fmaf(c1, k1[c], yf[c])));
             rhs_f32(R, u.tcf, Y, k4);
-            if (__builtin_expect(any_w, 0)) { to_omega_variable(k4, dtj, L.omega_mode); dts = __builtin_fmaf((float)B4, dtj, dts); }
-            if (PHASE) ps = __builtin_fmaf((float)B4, Y[0] * (any_w ? dtj : 1.0f), ps);
+            if (__builtin_expect(any_w, 0)) { to_omega_variable(k4, dtj, L.omega_mode); dts = __builtin_fmaf((float)B4, dtj, dts); settle(dts); }
+            if (PHASE) { ps = __builtin_fmaf((float)B4, Y[0] * (any_w ? dtj : 1.0f), ps); settle(ps); }
         }
         {
             const float c1 = hf * (float)A51, c2 = hf * (float)A52, c3 = hf * (float)A53, c4 = hf * (float)A54;
@@ -591,8 +596,8 @@ struct F32Split {
                 Y[c] = __builtin_fmaf(c4, k4[c], __builtin_fmaf(c3, k3[c],
                        __builtin_fmaf(c2, k2[c], __builtin_fmaf(c1, k1[c], yf[c]))));
             rhs_f32(R, u.tcf, Y, k5);
-            if (__builtin_expect(any_w, 0)) { to_omega_variable(k5, dtj, L.omega_mode); dts = __builtin_fmaf((float)B5, dtj, dts); }
-            if (PHASE) ps = __builtin_fmaf((float)B5, Y[0] * (any_w ? dtj : 1.0f), ps);
+            if (__builtin_expect(any_w, 0)) { to_omega_variable(k5, dtj, L.omega_mode); dts = __builtin_fmaf((float)B5, dtj, dts); settle(dts); }
+            if (PHASE) { ps = __builtin_fmaf((float)B5, Y[0] * (any_w ? dtj : 1.0f), ps); settle(ps); }
         }
         {
             const float c1 = hf * (float)A61, c2 = hf * (float)A62, c3 = hf * (float)A63, c4 = hf * (float)A64,
@@ -602,8 +607,8 @@ struct F32Split {
                 Y[c] = __builtin_fmaf(c5, k5[c], __builtin_fmaf(c4, k4[c], __builtin_fmaf(c3, k3[c],
                        __builtin_fmaf(c2, k2[c], __builtin_fmaf(c1, k1[c], yf[c])))));
             rhs_f32(R, u.tcf, Y, k6);
-            if (__builtin_expect(any_w, 0)) { to_omega_variable(k6, dtj, L.omega_mode); dts = __builtin_fmaf((float)B6, dtj, dts); }
-            if (PHASE) ps = __builtin_fmaf((float)B6, Y[0] * (any_w ? dtj : 1.0f), ps);
+            if (__builtin_expect(any_w, 0)) { to_omega_variable(k6, dtj, L.omega_mode); dts = __builtin_fmaf((float)B6, dtj, dts); settle(dts); }
+            if (PHASE) { ps = __builtin_fmaf((float)B6, Y[0] * (any_w ? dtj : 1.0f), ps); settle(ps); }
         }
         // 5th-order increment D (FP32), the stage-7 point, and the error sum
         float D[10], Ep[10];
@@ -754,8 +759,8 @@ struct F32State {
 #pragma unroll
             for (int c = 0; c < 10; ++c) Y[c] = __builtin_fmaf(c2, k2[c], __builtin_fmaf(c1, k1[c], yf[c]));
             rhs_f32(R, u.tcf, Y, k3);
-            if (__builtin_expect(any_w, 0)) { to_omega_variable(k3, dtj, L.omega_mode); dts = __builtin_fmaf((float)B3, dtj, dts); }
-            if (PHASE) ps = __builtin_fmaf((float)B3, Y[0] * (any_w ? dtj : 1.0f), ps);
+            if (__builtin_expect(any_w, 0)) { to_omega_variable(k3, dtj, L.omega_mode); dts = __builtin_fmaf((float)B3, dtj, dts); settle(dts); }
+            if (PHASE) { ps = __builtin_fmaf((float)B3, Y[0] * (any_w ? dtj : 1.0f), ps); settle(ps); }
         }
         {
             const float c1 = hf * (float)A41, c2 = hf * (float)A42, c3 = hf * (float)A43;
@@ -763,8 +768,8 @@ struct F32State {
             for (int c = 0; c < 10; ++c)
                 Y[c] = __builtin_fmaf(c3, k3[c], __builtin_fmaf(c2, k2[c], __builtin_fmaf(c1, k1[c], yf[c])));
             rhs_f32(R, u.tcf, Y, k4);
-            if (__builtin_expect(any_w, 0)) { to_omega_variable(k4, dtj, L.omega_mode); dts = __builtin_fmaf((float)B4, dtj, dts); }
-            if (PHASE) ps = __builtin_fmaf((float)B4, Y[0] * (any_w ? dtj : 1.0f), ps);
+            if (__builtin_expect(any_w, 0)) { to_omega_variable(k4, dtj, L.omega_mode); dts = __builtin_fmaf((float)B4, dtj, dts); settle(dts); }
+            if (PHASE) { ps = __builtin_fmaf((float)B4, Y[0] * (any_w ? dtj : 1.0f), ps); settle(ps); }
         }
         {
             const float c1 = hf * (float)A51, c2 = hf * (float)A52, c3 = hf * (float)A53, c4 = hf * (float)A54;
@@ -773,8 +778,8 @@ struct F32State {
                 Y[c] = __builtin_fmaf(c4, k4[c], __builtin_fmaf(c3, k3[c],
                        __builtin_fmaf(c2, k2[c], __builtin_fmaf(c1, k1[c], yf[c]))));
             rhs_f32(R, u.tcf, Y, k5);
-            if (__builtin_expect(any_w, 0)) { to_omega_variable(k5, dtj, L.omega_mode); dts = __builtin_fmaf((float)B5, dtj, dts); }
-            if (PHASE) ps = __builtin_fmaf((float)B5, Y[0] * (any_w ? dtj : 1.0f), ps);
+            if (__builtin_expect(any_w, 0)) { to_omega_variable(k5, dtj, L.omega_mode); dts = __builtin_fmaf((float)B5, dtj, dts); settle(dts); }
+            if (PHASE) { ps = __builtin_fmaf((float)B5, Y[0] * (any_w ? dtj : 1.0f), ps); settle(ps); }
         }
         {
             const float c1 = hf * (float)A61, c2 = hf * (float)A62, c3 = hf * (float)A63, c4 = hf * (float)A64,
@@ -784,8 +789,8 @@ struct F32State {
                 Y[c] = __builtin_fmaf(c5, k5[c], __builtin_fmaf(c4, k4[c], __builtin_fmaf(c3, k3[c],
                        __builtin_fmaf(c2, k2[c], __builtin_fmaf(c1, k1[c], yf[c])))));
             rhs_f32(R, u.tcf, Y, k6);
-            if (__builtin_expect(any_w, 0)) { to_omega_variable(k6, dtj, L.omega_mode); dts = __builtin_fmaf((float)B6, dtj, dts); }
-            if (PHASE) ps = __builtin_fmaf((float)B6, Y[0] * (any_w ? dtj : 1.0f), ps);
+            if (__builtin_expect(any_w, 0)) { to_omega_variable(k6, dtj, L.omega_mode); dts = __builtin_fmaf((float)B6, dtj, dts); settle(dts); }
+            if (PHASE) { ps = __builtin_fmaf((float)B6, Y[0] * (any_w ? dtj : 1.0f), ps); settle(ps); }
         }
         // 5th-order increment D (FP32), the stage-7 point, and the error sum
         float D[10], Ep[10];
@@ -1219,7 +1224,7 @@ __device__ __forceinline__ void reverse_step(const Row& R, const TermConsts& tc,
         /* compiler defers them to the end of the step and keeps every */                         \
         /* stage's operands alive until then (~700 AGPR moves and scratch */                      \
         /* spills per step) */                                                                   \
-        _Pragma("unroll") for (int i = 0; i < NROW; ++i) __asm__ volatile("" : "+v"(rb.v[i]));   \
+        _Pragma("unroll") for (int i = 0; i < NROW; ++i) settle(rb.v[i]);                          \
         if (last) {                                                                              \
             double f[10];                                                                        \
             rhs<Row, false>(R, tc, lb, Yi, f);                                                   \
