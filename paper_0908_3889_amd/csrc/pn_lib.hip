@@ -154,8 +154,8 @@ __device__ int read_input(const Io& io, const Uni& u, int64_t idx, double* y, do
 
 // mean_c (e_c / sc_c)^2 with sc_c = tol + tol max(|y_c|, |ynew_c|): the squared
 // RMS error norm z = err^2 of the error estimate e (the FP64 stepper passes
-// e/h and scales the result by h^2).  One reciprocal per component: the FP32
-// modes, whose tighter register budget the grouped form below would spill.
+// e/h and scales the result by h^2).  One reciprocal per component: the
+// FP32-state stepper (the grouped forms below fall back to the same sum).
 __device__ __forceinline__ double error_norm_each(const Uni& u, const double* y, const double* ynew, const double* e) {
     double z = 0.0;
 #pragma unroll
@@ -163,6 +163,38 @@ __device__ __forceinline__ double error_norm_each(const Uni& u, const double* y,
         const double sc = __builtin_fma(u.tol, fmax_abs(y[c], ynew[c]), u.tol);
         const double q = e[c] * rcp_1step(sc);
         z = __builtin_fma(q, q, z);
+    }
+    return z * 0.1;
+}
+
+// The same norm with the reciprocals taken in pairs (1/s0 = s1 / (s0 s1)):
+// the FP32-split stepper, where it saves 2 % of the kernel time without
+// spilling at 3 waves per SIMD (the FP32-state stepper measured no gain).
+// Lanes with a pair product outside the normal range take one reciprocal per
+// component.
+__device__ __forceinline__ double error_norm_pairs(const Uni& u, const double* y, const double* ynew, const double* e) {
+    double z = 0.0;
+    bool bad = false;
+#pragma unroll
+    for (int c = 0; c < 10; c += 2) {
+        const double s0 = __builtin_fma(u.tol, fmax_abs(y[c], ynew[c]), u.tol);
+        const double s1 = __builtin_fma(u.tol, fmax_abs(y[c + 1], ynew[c + 1]), u.tol);
+        const double p = s0 * s1;
+        bad = bad || __builtin_amdgcn_class(p, 0x2ff);   // every class but +normal
+        const double r = rcp_1step(p);
+        const double q0 = e[c] * (r * s1), q1 = e[c + 1] * (r * s0);
+        z = __builtin_fma(q0, q0, z);
+        z = __builtin_fma(q1, q1, z);
+    }
+    if (__builtin_expect(__ballot(bad) != 0, 0)) {
+        if (bad) {
+            z = 0.0;
+#pragma unroll
+            for (int c = 0; c < 10; ++c) {
+                const double q = e[c] * rcp_1step(__builtin_fma(u.tol, fmax_abs(y[c], ynew[c]), u.tol));
+                z = __builtin_fma(q, q, z);
+            }
+        }
     }
     return z * 0.1;
 }
@@ -632,7 +664,7 @@ struct F32Split {
         double e[10];
 #pragma unroll
         for (int c = 0; c < 10; ++c) e[c] = (double)(hf * __builtin_fmaf((float)E7, k7[c], Ep[c]));
-        const double z = error_norm_each(u, L.y, ynew, e);
+        const double z = error_norm_pairs(u, L.y, ynew, e);
         bool fin = (GEN && u.fixed) || !__builtin_isnan(z);
 #pragma unroll
         for (int c = 0; c < 10; ++c) fin = fin && finite(ynew[c]) && __builtin_isfinite(k7[c]);
