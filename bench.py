@@ -302,15 +302,18 @@ def _ordered_run(api, pop, d, opts, out, stream, order: bool = True):
     import torch
     if not order:
         api.set_order(opts, None)
+        api.set_packed(opts, None)
         return lambda: api.pn_integrate(d["m"], d["S"], d["L"], d["omega0"], pop["omega_f"], pop["tol"], opts,
                                         out=out, stream=stream)
     buf = torch.empty((pop["n"],), dtype=torch.int32, device="cuda")
     ws = api.cost_order_workspace(pop["n"])
+    packed = api.packed_inputs(pop["n"])
     api.set_order(opts, buf)
+    api.set_packed(opts, packed)
 
     def run():
         api.pn_cost_order(d["m"], d["S"], d["L"], d["omega0"], pop["omega_f"], out=buf, workspace=ws,
-                          stream=stream)
+                          packed=packed, stream=stream)
         api.pn_integrate(d["m"], d["S"], d["L"], d["omega0"], pop["omega_f"], pop["tol"], opts, out=out,
                          stream=stream)
     return run
@@ -346,6 +349,7 @@ def leg_fp32split(api, pop, d, ref64: dict, stream, reps: int = 5, precision: st
     }
     # the orbital phase, integrated alongside in both precisions (untimed)
     api.set_order(opts, None)
+    api.set_packed(opts, None)
     p32 = api.pn_integrate_phase(d["m"], d["S"], d["L"], d["omega0"], pop["omega_f"], pop["tol"], opts,
                                  stream=stream)
     p64 = api.pn_integrate_phase(d["m"], d["S"], d["L"], d["omega0"], pop["omega_f"], pop["tol"],
@@ -647,14 +651,17 @@ def main() -> int:
     cost_order = args.order == "cost" and args.schedule == "persistent"
     order_buf = torch.empty((pop["n"],), dtype=torch.int32, device="cuda") if cost_order else None
     order_ws = api.cost_order_workspace(pop["n"]) if cost_order else None
+    # the same pass writes the inputs as 128-byte records, which the refills read
+    packed_buf = api.packed_inputs(pop["n"]) if cost_order else None
     api.set_order(opts, order_buf)
+    api.set_packed(opts, packed_buf)
 
     def step(kev=None):
         """One pass over the workload; kev: a list that receives the HIP
         events around the integration kernel alone (the dominant kernel)."""
         if cost_order:
             api.pn_cost_order(d["m"], d["S"], d["L"], d["omega0"], pop["omega_f"], out=order_buf,
-                              workspace=order_ws, stream=stream)
+                              workspace=order_ws, packed=packed_buf, stream=stream)
         if kev is not None:
             kev.append(torch.cuda.Event(enable_timing=True))
             kev[-1].record(stream)
@@ -736,7 +743,8 @@ def main() -> int:
                    "waves_per_simd": opts.waves_per_simd or None, "autotuned": tuned},
         "kernel_ms": avg_ms,
         "step_ms_events": step_ms,
-        "order": "cost (pn_cost_order inside every step)" if cost_order else "natural",
+        "order": ("cost (pn_cost_order inside every step; the same pass packs the inputs into 128-byte records "
+                  "that the refills read)") if cost_order else "natural",
         "rhs_evals_per_s": float(steps[2].astype(np.int64).sum()) / (avg_ms * 1e-3),
         "attempted_steps": attempted_steps(steps),
         "accepted_steps": int(steps[0].astype(np.int64).sum()),

@@ -134,6 +134,15 @@ typedef struct pn_opts {
                               slot integrates nothing); an index missing from the
                               array leaves its outputs unwritten.  Requires
                               n <= 2^31 - 1. */
+    const double* packed;  /* NULL, or device double [n][16], 16-byte aligned: each
+                              inspiral's inputs as one 128-byte record (m1, m2,
+                              omega0, S1, S2, L_hat, then four zeros), as
+                              pn_cost_order writes them.  When set, the kernels
+                              read the inputs from here (one cache line per
+                              inspiral) instead of from m, S0, L0, omega0 (whose
+                              pointers are still checked); the records must hold
+                              the same inputs, and the results are then the
+                              same, bit for bit.  PN_EINVAL if misaligned. */
 } pn_opts;
 
 /*
@@ -187,15 +196,20 @@ int pn_integrate(int64_t n, int64_t ld,
  * Inputs as pn_integrate (device, SoA, leading dimension ld); omega_f <= 0
  * ranks by 1/omega0 alone.  order [n]: device int32 output, a permutation of
  * 0 .. n-1.  workspace: device scratch of at least
- * pn_cost_order_workspace_bytes(n) bytes, caller-owned.  Requires
- * n <= 2^31 - 1; PN_EINVAL for bad sizes, NULL pointers or a small
- * workspace.  The ranking only changes the speed of pn_integrate, never its
- * results.
+ * pn_cost_order_workspace_bytes(n) bytes, caller-owned.  packed: NULL, or a
+ * device double [n][16] output (16-byte aligned, caller-owned) that receives
+ * the inputs as the 128-byte records of pn_opts.packed, written by the same
+ * pass that reads them for the keys: in the cost order, the lanes of a
+ * refill read inspirals far apart in memory, and from the SoA arrays each of
+ * their 12 input words costs a cache line of its own.  Requires
+ * n <= 2^31 - 1; PN_EINVAL for bad sizes, NULL pointers, a small workspace or
+ * a misaligned packed.  The ranking only changes the speed of pn_integrate,
+ * never its results.
  */
 size_t pn_cost_order_workspace_bytes(int64_t n);
 int pn_cost_order(int64_t n, int64_t ld, const double* m, const double* S0, const double* L0,
                   const double* omega0, double omega_f, int32_t* order, void* workspace,
-                  size_t ws_bytes, void* stream);
+                  size_t ws_bytes, double* packed, void* stream);
 
 /*
  * The check of GPU results against the CPU on a subset (Sec. III: kernel

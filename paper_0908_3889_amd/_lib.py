@@ -47,6 +47,7 @@ class PnOpts(C.Structure):
         ("refill_min", C.c_int32),
         ("precision", C.c_int32),
         ("order", C.c_void_p),
+        ("packed", C.c_void_p),
     ]
 
 
@@ -83,7 +84,7 @@ def load():
     L.pn_integrate.restype = C.c_int
     L.pn_cost_order_workspace_bytes.argtypes = [i64]
     L.pn_cost_order_workspace_bytes.restype = C.c_size_t
-    L.pn_cost_order.argtypes = [i64, i64, vp, vp, vp, vp, dbl, vp, vp, C.c_size_t, vp]
+    L.pn_cost_order.argtypes = [i64, i64, vp, vp, vp, vp, dbl, vp, vp, C.c_size_t, vp, vp]
     L.pn_cost_order.restype = C.c_int
     L.pn_check_integrate_host.argtypes = [i64, i64, vp, vp, vp, vp, dbl, dbl, popts, vp, vp, vp, vp, C.c_int32]
     L.pn_check_integrate_host.restype = C.c_int

@@ -54,9 +54,10 @@ def _stream(stream):
 
 def make_opts(*, h0=0.0, h_fixed=0.0, t_end=0.0, max_steps=0, terms=_lib.PN_TERM_ALL,
               theta_literal=0, schedule="persistent", block=0, waves_per_simd=0,
-              refill_min=0, precision="fp64", order=None) -> PnOpts:
-    """pn_opts; order: None or an int32 device tensor [n] (pn_cost_order),
-    kept alive by the returned struct."""
+              refill_min=0, precision="fp64", order=None, packed=None) -> PnOpts:
+    """pn_opts; order: None or an int32 device tensor [n] (pn_cost_order);
+    packed: None or the float64 [n, 16] input records pn_cost_order wrote;
+    both kept alive by the returned struct."""
     o = PnOpts()
     o.h0, o.h_fixed, o.t_end = float(h0), float(h_fixed), float(t_end)
     o.max_steps, o.terms, o.theta_literal = int(max_steps), int(terms), int(theta_literal)
@@ -64,7 +65,27 @@ def make_opts(*, h0=0.0, h_fixed=0.0, t_end=0.0, max_steps=0, terms=_lib.PN_TERM
     o.block, o.waves_per_simd, o.refill_min = int(block), int(waves_per_simd), int(refill_min)
     o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     set_order(o, order)
+    set_packed(o, packed)
     return o
+
+
+def set_packed(o: PnOpts, packed) -> PnOpts:
+    """Point o.packed at float64 [n, 16] input records (or clear it with None)."""
+    if packed is None:
+        o.packed = None
+        o._packed_ref = None
+        return o
+    if packed.dtype != torch.float64 or packed.dim() != 2 or packed.shape[1] != 16 or not packed.is_contiguous():
+        raise ValueError("packed must be a contiguous float64 [n, 16] tensor")
+    o.packed = C.c_void_p(packed.data_ptr())
+    o._packed_ref = packed
+    return o
+
+
+def packed_inputs(n: int, device=None):
+    """A device buffer for the 128-byte input records of pn_cost_order."""
+    dev = device or torch.device("cuda", torch.cuda.current_device())
+    return torch.empty((int(n), 16), dtype=torch.float64, device=dev)
 
 
 def set_order(o: PnOpts, order) -> PnOpts:
@@ -87,9 +108,11 @@ def cost_order_workspace(n: int, device=None):
     return torch.empty((max(b, 1),), dtype=torch.uint8, device=dev)
 
 
-def pn_cost_order(m, S0, L0, omega0, omega_f, out=None, workspace=None, stream=None):
+def pn_cost_order(m, S0, L0, omega0, omega_f, out=None, workspace=None, packed=None, stream=None):
     """The longest-first hand-out order of the inspirals (int32 [n] on the
-    device) from the leading-order step estimate of pn_cost_order."""
+    device) from the leading-order step estimate of pn_cost_order; with
+    packed (a float64 [n, 16] buffer, see packed_inputs) the same pass also
+    writes the inputs as the records of pn_opts.packed."""
     n = int(omega0.shape[0])
     _soa(omega0, 1, n, "omega0")
     _soa(m, 2, n, "m"); _soa(S0, 6, n, "S0"); _soa(L0, 3, n, "L0")
@@ -101,9 +124,12 @@ def pn_cost_order(m, S0, L0, omega0, omega_f, out=None, workspace=None, stream=N
         out = torch.empty((n,), dtype=torch.int32, device=omega0.device)
     if workspace is None:
         workspace = cost_order_workspace(n, omega0.device)
+    if packed is not None and (packed.dtype != torch.float64 or tuple(packed.shape) != (n, 16)
+                               or not packed.is_contiguous()):
+        raise ValueError("packed must be a contiguous float64 [n, 16] tensor")
     p = lambda t: C.c_void_p(t.data_ptr())
     rc = load().pn_cost_order(n, ld, p(m), p(S0), p(L0), p(omega0), float(omega_f), p(out), p(workspace),
-                              int(workspace.numel()), _stream(stream))
+                              int(workspace.numel()), None if packed is None else p(packed), _stream(stream))
     check(rc, "pn_cost_order")
     return out
 

@@ -81,6 +81,7 @@ struct Io {
     double* __restrict__ dots;
     double* __restrict__ phase;   // orbital phase at t_final, or null
     const int32_t* __restrict__ order;   // hand-out order of the inspirals, or null
+    const double* __restrict__ packed;   // inputs as [n][16] records, or null
 };
 
 // What a persistent launch reads only when it refills lanes or writes
@@ -130,17 +131,26 @@ __device__ void write_out(const Io& io, const Uni& u, int64_t i, const double* y
 
 // Read inspiral idx into y and the masses; returns 0, or the status of an
 // inspiral that is finished at once (bad input, or omega0 >= omega_f), whose
-// outputs are then already written.
+// outputs are then already written.  From the packed record when there is
+// one (six 16-byte loads from one cache line), else from the SoA inputs.
 template <bool PHASE = false>
 __device__ int read_input(const Io& io, const Uni& u, int64_t idx, double* y, double& m1, double& m2) {
     const int64_t ld = u.ld;
-    m1 = io.m[idx];
-    m2 = io.m[ld + idx];
-    y[0] = io.w0[idx];
+    if (io.packed) {
+        const double2* r = (const double2*)(io.packed + idx * 16);
+        const double2 a = r[0], b = r[1], c = r[2], d = r[3], e = r[4], f = r[5];
+        m1 = a.x; m2 = a.y;
+        y[0] = b.x; y[1] = b.y; y[2] = c.x; y[3] = c.y; y[4] = d.x;
+        y[5] = d.y; y[6] = e.x; y[7] = e.y; y[8] = f.x; y[9] = f.y;
+    } else {
+        m1 = io.m[idx];
+        m2 = io.m[ld + idx];
+        y[0] = io.w0[idx];
 #pragma unroll
-    for (int c = 0; c < 6; ++c) y[1 + c] = io.S0[c * ld + idx];
+        for (int c = 0; c < 6; ++c) y[1 + c] = io.S0[c * ld + idx];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) y[7 + c] = io.L0[c * ld + idx];
+        for (int c = 0; c < 3; ++c) y[7 + c] = io.L0[c * ld + idx];
+    }
     bool bad = !(m1 > 0.0) || !(m2 > 0.0) || !(y[0] > 0.0) || !finite(m1) || !finite(m2);
 #pragma unroll
     for (int c = 0; c < 10; ++c) bad = bad || !finite(y[c]);
@@ -1806,6 +1816,7 @@ static int integrate_impl(int64_t n, int64_t ld, const double* m, const double* 
     if (o.terms < 0 || o.terms > PN_TERM_ALL) return PN_EINVAL;
     if (o.theta_literal != 0 && o.theta_literal != 1) return PN_EINVAL;
     if (o.order && n > INT32_MAX) return PN_EINVAL;
+    if (((uintptr_t)o.packed & 15) != 0) return PN_EINVAL;
     if (tape) {
         if (o.precision != PN_PREC_FP64 || tend) return PN_EINVAL;
         if (cap_steps < 1 || cap_steps > (1 << 28) || ckpt_every < 1 || ckpt_every > 4096) return PN_EINVAL;
@@ -1845,6 +1856,7 @@ static int integrate_impl(int64_t n, int64_t ld, const double* m, const double* 
     io.y = y_final; io.t = t_final; io.steps = steps; io.status = status; io.dots = dots;
     io.phase = phase;
     io.order = o.order;
+    io.packed = o.packed;
 
     hipStream_t s = (hipStream_t)stream;
     if (o.schedule == PN_SCHED_STATIC) {

@@ -38,7 +38,8 @@ __device__ __forceinline__ double normal_part(double v0, double v1, double v2, d
 
 __global__ void cost_key_kernel(int64_t n, int64_t ld, const double* __restrict__ m, const double* __restrict__ S,
                                 const double* __restrict__ L, const double* __restrict__ w0, double omega_f,
-                                uint16_t* __restrict__ key, int32_t* __restrict__ idx) {
+                                uint16_t* __restrict__ key, int32_t* __restrict__ idx,
+                                double* __restrict__ packed) {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
     const double m1 = m[i], m2 = m[ld + i], w = w0[i];
@@ -46,6 +47,19 @@ __global__ void cost_key_kernel(int64_t n, int64_t ld, const double* __restrict_
     const double s20 = S[3 * ld + i], s21 = S[4 * ld + i], s22 = S[5 * ld + i];
     const double l0 = L[i], l1 = L[ld + i], l2 = L[2 * ld + i];
     idx[i] = (int32_t)i;
+    if (packed) {
+        // the inputs as one 128-byte record: each lane's eight 16-byte stores
+        // fill its own cache line, so the lines leave L2 whole
+        double2* r = (double2*)(packed + i * 16);
+        r[0] = make_double2(m1, m2);
+        r[1] = make_double2(w, s10);
+        r[2] = make_double2(s11, s12);
+        r[3] = make_double2(s20, s21);
+        r[4] = make_double2(s22, l0);
+        r[5] = make_double2(l1, l2);
+        r[6] = make_double2(0.0, 0.0);
+        r[7] = make_double2(0.0, 0.0);
+    }
     double k = 0.0;       // inputs the integrator refuses, or that finish at once: last
     if (m1 > 0.0 && m2 > 0.0 && w > 0.0 && (omega_f <= 0.0 || w < omega_f)) {
         const double M = m1 + m2;
@@ -94,11 +108,13 @@ size_t pn_cost_order_workspace_bytes(int64_t n) {
 }
 
 int pn_cost_order(int64_t n, int64_t ld, const double* m, const double* S0, const double* L0, const double* omega0,
-                  double omega_f, int32_t* order, void* workspace, size_t ws_bytes, void* stream) {
+                  double omega_f, int32_t* order, void* workspace, size_t ws_bytes, double* packed,
+                  void* stream) {
     if (n < 0 || n > INT32_MAX || ld < n || ld > PN_MAX_N) return PN_EINVAL;
     if (!(omega_f == omega_f)) return PN_EINVAL;
     if (n == 0) return PN_OK;
     if (!m || !S0 || !L0 || !omega0 || !order || !workspace) return PN_EINVAL;
+    if (((uintptr_t)packed & 15) != 0) return PN_EINVAL;
     const size_t need = pn_cost_order_workspace_bytes(n);
     if (need == 0 || ws_bytes < need) return PN_EINVAL;
     hipStream_t s = (hipStream_t)stream;
@@ -111,7 +127,7 @@ int pn_cost_order(int64_t n, int64_t ld, const double* m, const double* S0, cons
     size_t tmp_bytes = need - 3 * a;
     const unsigned grid = (unsigned)((n + kBlock - 1) / kBlock);
     hipLaunchKernelGGL(cost_key_kernel, dim3(grid), dim3(kBlock), 0, s, n, ld, m, S0, L0, omega0, omega_f, key_in,
-                       idx_in);
+                       idx_in, packed);
     if (hipGetLastError() != hipSuccess) return PN_EHIP;
     if (rocprim::radix_sort_pairs_desc(tmp, tmp_bytes, key_in, key_out, idx_in, order, (size_t)n, 0, 16, s) !=
         hipSuccess)

@@ -44,9 +44,9 @@ def test_strerror_and_version(lib):
 
 def test_opts_struct_layout_matches_header():
     from paper_0908_3889_amd._lib import PnOpts
-    # 3 doubles, one int64, seven int32 padded to 8 bytes, one pointer
-    assert C.sizeof(PnOpts) == 3 * 8 + 8 + 7 * 4 + 4 + 8
-    assert PnOpts.order.offset == 64
+    # 3 doubles, one int64, seven int32 padded to 8 bytes, two pointers
+    assert C.sizeof(PnOpts) == 3 * 8 + 8 + 7 * 4 + 4 + 2 * 8
+    assert PnOpts.order.offset == 64 and PnOpts.packed.offset == 72
     names = [f[0] for f in PnOpts._fields_]
     src = open(os.path.join(ROOT, "include", "pn.h")).read()
     body = src[src.index("typedef struct pn_opts"):src.index("} pn_opts;")]
@@ -77,6 +77,8 @@ def test_invalid_arguments_return_einval_without_a_device(lib):
     assert call(10, 10, opt=bad) == PN_EINVAL
     bad = PnOpts(); bad.precision = 3
     assert call(10, 10, opt=bad) == PN_EINVAL
+    bad = PnOpts(); bad.packed = C.c_void_p(0x1008)  # input records must be 16-byte aligned
+    assert call(10, 10, opt=bad) == PN_EINVAL
     assert call(0, 0) == PN_OK                       # empty batch: nothing to do
     ph = lambda n, ld, out, tol=1e-8: lib.pn_integrate_phase(
         n, ld, fake, fake, fake, fake, 0.05, tol, C.byref(o), fake, fake, fake, fake, z, out, z)
@@ -106,13 +108,14 @@ def test_cost_order_argument_checks_without_a_device(lib):
     assert lib.pn_cost_order_workspace_bytes(0) == 0
     assert lib.pn_cost_order_workspace_bytes(-1) == 0
     assert lib.pn_cost_order_workspace_bytes(1 << 31) == 0
-    call = lambda n, ld, ptr=fake, ws=1 << 20, wf=0.05: lib.pn_cost_order(
-        n, ld, ptr, ptr, ptr, ptr, wf, ptr, ptr, ws, z)
+    call = lambda n, ld, ptr=fake, ws=1 << 20, wf=0.05, packed=z: lib.pn_cost_order(
+        n, ld, ptr, ptr, ptr, ptr, wf, ptr, ptr, ws, packed, z)
     assert call(-1, 0) == PN_EINVAL
     assert call(10, 5) == PN_EINVAL
     assert call(1 << 31, 1 << 31) == PN_EINVAL
     assert call(10, 10, wf=float("nan")) == PN_EINVAL
     assert call(10, 10, ptr=z) == PN_EINVAL
+    assert call(10, 10, packed=C.c_void_p(0x1008)) == PN_EINVAL   # misaligned records
     assert call(0, 0, ptr=z) == PN_OK
 
 

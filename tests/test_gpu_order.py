@@ -112,3 +112,61 @@ def test_entries_outside_the_range_are_skipped():
         keep[[10, 300]] = False
         np.testing.assert_array_equal(out["y"].cpu().numpy()[:, keep], ref["y"].cpu().numpy()[:, keep])
         np.testing.assert_array_equal(st[keep], ref["status"].cpu().numpy()[keep])
+
+
+def test_packed_records_hold_the_inputs():
+    """pn_cost_order's packed output: per inspiral m1, m2, omega0, S1, S2,
+    L_hat and four zeros, bit for bit, on a size that is not a multiple of
+    the block (and with a bad input and one done at start)."""
+    from paper_0908_3889_amd import api
+    pop = P.generate("q1to4_1M", 5003)
+    pop["omega0"] = pop["omega0"].copy(); pop["m"] = pop["m"].copy()
+    pop["omega0"][7] = 0.06
+    pop["m"][1, 11] = 0.0
+    d = api.to_device(pop)
+    packed = api.packed_inputs(pop["n"])
+    packed.fill_(float("nan"))
+    api.pn_cost_order(d["m"], d["S"], d["L"], d["omega0"], pop["omega_f"], packed=packed)
+    torch.cuda.synchronize()
+    got = packed.cpu().numpy()
+    want = np.concatenate([pop["m"], pop["omega0"][None], pop["S"], pop["L"], np.zeros((4, pop["n"]))]).T
+    np.testing.assert_array_equal(got, want)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32split", "fp32"])
+def test_packed_inputs_give_the_same_results(precision):
+    """Reading the inputs from the packed records (with the cost order, in
+    index order, the static schedule, the phase kernel and the no-allocation
+    entry point) gives every inspiral the bits of the SoA run."""
+    from paper_0908_3889_amd import api
+    pop = P.generate("batching_4M", 3001)
+    pop["omega0"] = pop["omega0"].copy(); pop["S"] = pop["S"].copy()
+    pop["omega0"][5] = 0.06                   # done at start
+    pop["S"][2, 9] = np.nan                   # bad input
+    d = api.to_device(pop)
+    ref = api.pn_integrate(d["m"], d["S"], d["L"], d["omega0"], pop["omega_f"], pop["tol"],
+                           api.make_opts(precision=precision))
+    packed = api.packed_inputs(pop["n"])
+    order = api.pn_cost_order(d["m"], d["S"], d["L"], d["omega0"], pop["omega_f"], packed=packed)
+    runs = {"cost order": api.make_opts(precision=precision, order=order, packed=packed),
+            "index order": api.make_opts(precision=precision, packed=packed),
+            "static": api.make_opts(precision=precision, schedule="static", packed=packed)}
+    for name, opts in runs.items():
+        out = api.pn_integrate(d["m"], d["S"], d["L"], d["omega0"], pop["omega_f"], pop["tol"], opts)
+        torch.cuda.synchronize()
+        for k in KEYS:
+            np.testing.assert_array_equal(out[k].cpu().numpy(), ref[k].cpu().numpy(), err_msg=f"{name}: {k}")
+    assert ref["status"][5].item() == 1 and ref["status"][9].item() == -4
+    ph_ref = api.pn_integrate_phase(d["m"], d["S"], d["L"], d["omega0"], pop["omega_f"], pop["tol"],
+                                    api.make_opts(precision=precision))
+    ph = api.pn_integrate_phase(d["m"], d["S"], d["L"], d["omega0"], pop["omega_f"], pop["tol"],
+                                api.make_opts(precision=precision, order=order, packed=packed))
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(ph["phase"].cpu().numpy(), ph_ref["phase"].cpu().numpy())
+    if precision == "fp64":
+        out = api.alloc_outputs(pop["n"])
+        api.pn_integrate_noalloc(d["m"], d["S"], d["L"], d["omega0"], pop["omega_f"], pop["tol"], out,
+                                 api.make_opts(order=order, packed=packed))
+        torch.cuda.synchronize()
+        for k in KEYS:
+            np.testing.assert_array_equal(out[k].cpu().numpy(), ref[k].cpu().numpy(), err_msg=f"noalloc: {k}")
