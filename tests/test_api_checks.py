@@ -72,3 +72,18 @@ def test_missing_library_fails_loudly_and_the_package_never_imports_the_oracle()
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, cwd=root, env=env, timeout=300)
     assert r.returncode == 0, r.stderr[-2000:]
     assert r.stdout.strip() == "raised"
+
+
+def test_packed_records_are_checked():
+    """opts.packed takes only a contiguous float64 [n, 16] tensor; None clears it."""
+    o = api.make_opts()
+    assert not o.packed
+    for bad in (torch.zeros(4, 12, dtype=torch.float64), torch.zeros(4, 16, dtype=torch.float32),
+                torch.zeros(16, 4, dtype=torch.float64).t(), torch.zeros(64, dtype=torch.float64)):
+        with pytest.raises(ValueError):
+            api.set_packed(o, bad)
+    good = torch.zeros(4, 16, dtype=torch.float64)
+    api.set_packed(o, good)
+    assert o.packed == good.data_ptr()
+    api.set_packed(o, None)
+    assert not o.packed
